@@ -1,0 +1,350 @@
+"""Pins for the CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: textbook
+identities (Clifford algebra, gauge covariance, sign(A)^2 = I), closed forms
+(free field in momentum space, Kenney-Laub closed form), special cases
+(mu = 0 Hermitian limit, Arnoldi breakdown on a plane wave) and brute force
+on tiny lattices.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import skinputs as si
+from oracle import dirac, rational, signfun, xstar, krylov, deflation
+
+RAGGED = (3, 4, 5, 6)
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300)
+
+
+# ---------------------------------------------------------------- gamma algebra
+def test_gamma_clifford_and_gamma5():
+    g = dirac.gammas()
+    for a in range(4):
+        assert np.allclose(g[a], g[a].conj().T)
+        for b in range(4):
+            ac = g[a] @ g[b] + g[b] @ g[a]
+            assert np.allclose(ac, 2 * np.eye(4) * (a == b))
+    g5 = dirac.gamma5()
+    assert np.allclose(g5, np.diag([1, 1, -1, -1]))
+    for a in range(4):
+        assert np.allclose(g5 @ g[a] + g[a] @ g5, 0)
+
+
+# ---------------------------------------------------------------- Kenney-Laub
+@pytest.mark.parametrize("s", [3, 5, 8, 10])
+def test_kl_partial_fractions_match_closed_form(s):
+    rng = np.random.default_rng(s)
+    t = rng.normal(size=200) * 2 + 1j * rng.normal(size=200) * 2
+    t = t[np.abs(t.real) > 0.05]
+    g0 = rational.kl_closed_form(t, s)
+    g1 = rational.kl_t2_form(t, s)
+    sig, om = rational.kl_first_order(s, 1.0)
+    g2 = rational.g_first_order(t, sig, om)
+    assert np.max(np.abs(g1 - g0)) < 1e-12
+    assert np.max(np.abs(g2 - g0)) < 1e-12
+    # scaled form: g_s(c x) from first-order poles at +-i tau/c, weights w/(2c)
+    c = 0.37
+    sig, om = rational.kl_first_order(s, c)
+    assert np.max(np.abs(rational.g_first_order(t, sig, om) - rational.kl_closed_form(c * t, s))) < 1e-12
+
+
+@pytest.mark.parametrize("s", [4, 8])
+def test_kl_structural_identities(s):
+    t = np.array([0.3 + 0.2j, 1.7 - 0.4j, 5.0 + 1.0j, -2.0 + 0.1j])
+    g = lambda u: rational.kl_closed_form(u, s)
+    assert abs(g(np.array([1.0]))[0] - 1) < 1e-15        # g_s(1) = 1
+    assert np.allclose(g(-t), -g(t))                     # odd
+    assert np.allclose(g(1 / t), g(t))                   # g_s(1/t) = g_s(t)
+    sig, om = rational.kl_first_order(s)
+    assert np.allclose(np.sort_complex(sig.conj()), np.sort_complex(sig))  # conjugation closed
+    assert np.allclose(om.imag, 0)
+    # sign-like: approaches +-1 exponentially in s on the positive / negative axis
+    x = np.linspace(0.2, 5, 50)
+    assert np.max(np.abs(rational.kl_closed_form(x, 40) - 1)) < 1e-10
+
+
+# ---------------------------------------------------------------- Wilson operator
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), RAGGED])
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+@pytest.mark.parametrize("anti", [True, False])
+def test_free_field_csr_matches_momentum_space(dims, mu, anti):
+    V = si.lattice_volume(dims)
+    A = dirac.hw_csr(si.unit_links(dims), dims, 0.25, mu, anti)
+    psi = si.gaussian_source(12 * V, 5)
+    ff = dirac.free_field_apply(psi, dims, 0.25, mu, anti)
+    assert rel(A @ psi, ff) < 1e-13
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), RAGGED])
+def test_gamma5_hermiticity_and_mu_zero_limit(dims):
+    U = si.gauge_links(dims, 0.5, 11)
+    A = dirac.hw_csr(U, dims, 0.2, 0.3)
+    B = dirac.hw_csr(U, dims, 0.2, -0.3)
+    assert abs(A.conj().T - B).max() < 1e-15        # H(mu)^H = H(-mu)
+    A0 = dirac.hw_csr(U, dims, 0.2, 0.0)
+    assert abs(A0.conj().T - A0).max() < 1e-15       # Hermitian at mu = 0
+    assert abs(A - A.conj().T).max() > 1e-3          # and not at mu != 0
+
+
+def _random_su3_field(V, seed):
+    return si.gauge_links((V, 1, 1, 1), 1.3, seed)[:, 0]
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), RAGGED])
+def test_gauge_covariance(dims):
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.7, 3)
+    Om = _random_su3_field(V, 4)                      # Omega(x)
+    fwd, _, _, _ = dirac.neighbours(dims)
+    Ug = np.einsum("sab,snbc,sndc->snad", Om, U, Om[fwd].conj())  # Om(x) U Om(x+nu)^+
+    psi = si.gaussian_source(12 * V, 6).reshape(V, 4, 3)
+    gpsi = np.einsum("sab,sib->sia", Om, psi).reshape(-1)
+    A = dirac.hw_csr(U, dims, 0.21, 0.4)
+    Ag = dirac.hw_csr(Ug, dims, 0.21, 0.4)
+    lhs = Ag @ gpsi
+    rhs = np.einsum("sab,sib->sia", Om, (A @ psi.reshape(-1)).reshape(V, 4, 3)).reshape(-1)
+    assert rel(lhs, rhs) < 1e-13
+
+
+def test_direct_site_loop_matches_csr_2x4():
+    """Brute force on 2x2x2x2 plus one odd extent: H_W applied by explicit
+    Python loops over sites and directions (a second, unvectorised reading
+    of the definition) equals the CSR matrix."""
+    dims = (2, 3, 2, 2)
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.6, 21)
+    psi = si.gaussian_source(12 * V, 22).reshape(V, 4, 3)
+    kappa, mu = 0.23, 0.35
+    g = dirac.gammas()
+    g5 = dirac.gamma5()
+    Lx, Ly, Lz, Lt = dims
+    out = np.zeros_like(psi)
+    for t in range(Lt):
+        for z in range(Lz):
+            for y in range(Ly):
+                for x in range(Lx):
+                    s = ((t * Lz + z) * Ly + y) * Lx + x
+                    acc = psi[s].copy()
+                    c = [x, y, z, t]
+                    for nu in range(4):
+                        cf = list(c); cf[nu] = (c[nu] + 1) % dims[nu]
+                        cb = list(c); cb[nu] = (c[nu] - 1) % dims[nu]
+                        sf = ((cf[3] * Lz + cf[2]) * Ly + cf[1]) * Lx + cf[0]
+                        sb = ((cb[3] * Lz + cb[2]) * Ly + cb[1]) * Lx + cb[0]
+                        ef = np.exp(mu) if nu == 3 else 1.0
+                        eb = np.exp(-mu) if nu == 3 else 1.0
+                        if nu == 3 and c[3] == Lt - 1:
+                            ef = -ef
+                        if nu == 3 and c[3] == 0:
+                            eb = -eb
+                        hop_f = (np.eye(4) - g[nu]) @ (U[s, nu] @ psi[sf].T).T
+                        hop_b = (np.eye(4) + g[nu]) @ (U[sb, nu].conj().T @ psi[sb].T).T
+                        acc = acc - kappa * (ef * hop_f + eb * hop_b)
+                    out[s] = g5 @ acc
+    A = dirac.hw_csr(U, dims, kappa, mu)
+    assert rel(A @ psi.reshape(-1), out.reshape(-1)) < 1e-14
+
+
+# ---------------------------------------------------------------- sign function
+@pytest.fixture(scope="module")
+def small_hw():
+    dims = (2, 2, 2, 2)
+    U = si.gauge_links(dims, 0.5, 2007)
+    return dirac.hw_dense(U, dims, 0.25, 0.3), dims, U
+
+
+def test_sign_schur_newton_eig_agree(small_hw):
+    A, _, _ = small_hw
+    S1 = signfun.sign_schur(A)
+    S2 = signfun.sign_newton(A)
+    S3 = signfun.sign_eig(A)
+    assert rel(S1, S2) < 1e-12
+    assert rel(S1, S3) < 1e-10
+    n = A.shape[0]
+    assert np.linalg.norm(S1 @ S1 - np.eye(n)) / np.sqrt(n) < 1e-12
+    assert np.linalg.norm(S1 @ A - A @ S1) / np.linalg.norm(A) < 1e-12
+
+
+def test_sign_mu_zero_limit_is_eigh():
+    dims = (2, 2, 2, 2)
+    A = dirac.hw_dense(si.gauge_links(dims, 0.5, 9), dims, 0.25, 0.0)
+    w, W = np.linalg.eigh(A)
+    ref = (W * np.sign(w)) @ W.conj().T
+    assert rel(signfun.sign_schur(A), ref) < 1e-12
+    assert rel(signfun.sign_newton(A), ref) < 1e-12
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 3, 2, 4)])
+def test_free_field_sign_closed_form(dims):
+    V = si.lattice_volume(dims)
+    A = dirac.hw_dense(si.unit_links(dims), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 7)
+    ref = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: np.sign(l.real))
+    assert rel(signfun.sign_schur(A) @ b, ref) < 1e-12
+
+
+# ---------------------------------------------------------------- x* and rational g
+def test_xstar_free_field_closed_form_4x4():
+    dims = (4, 4, 4, 4)
+    V = si.lattice_volume(dims)
+    A = dirac.hw_dense(si.unit_links(dims), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 8)
+    s, c = 5, 0.8
+    sig, om = rational.kl_first_order(s, c)
+    x = xstar.xstar_dense(A, b, sig, om)
+    ref = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: rational.kl_closed_form(c * l, s))
+    assert rel(x, ref) < 1e-12
+    # sparse LU route agrees too
+    Asp = dirac.hw_csr(si.unit_links(dims), dims, 0.25, 0.3)
+    assert rel(xstar.xstar_sparse(Asp, b, sig, om), ref) < 1e-12
+
+
+def test_xstar_brute_force_2x4(small_hw):
+    """At 2^4 compute g(A) b from the eigendecomposition and compare."""
+    A, dims, _ = small_hw
+    b = si.gaussian_source(A.shape[0], 9)
+    sig, om = rational.kl_first_order(5, 0.9)
+    lam, W = np.linalg.eig(A)
+    ref = W @ (rational.g_first_order(lam, sig, om) * np.linalg.solve(W, b))
+    assert rel(xstar.xstar_dense(A, b, sig, om), ref) < 1e-11
+
+
+# ---------------------------------------------------------------- deflation
+def test_lr_deflation_projector_properties(small_hw):
+    A, _, _ = small_hw
+    R, L, lam, F = deflation.lr_dense(A, 12)
+    P = R @ L.conj().T
+    assert np.linalg.norm(P @ P - P) < 1e-11
+    assert np.linalg.norm(A @ P - P @ A) / np.linalg.norm(A) < 1e-11
+    assert np.linalg.norm(L.conj().T @ R - np.eye(12)) < 1e-11
+    res_r, res_l, bi = deflation.projector_checks(A, R, L, lam)
+    assert max(res_r, res_l, bi) < 1e-11
+    # the selected eigenvalues are the 12 of smallest modulus
+    allv = np.sort(np.abs(np.linalg.eigvals(A)))
+    assert np.allclose(np.sort(np.abs(lam)), allv[:12])
+    # x_P = sign(A) P b exactly
+    b = si.gaussian_source(A.shape[0], 10)
+    assert rel(xstar.x_p(b, R, L, F), signfun.sign_schur(A) @ (P @ b)) < 1e-11
+
+
+def test_deflated_xstar_equals_sign_on_deflated_part(small_hw):
+    """Deflating every eigenvalue makes x* = sign(A) b exactly."""
+    A, _, _ = small_hw
+    n = A.shape[0]
+    R, L, lam, F = deflation.lr_dense(A, n - 1)
+    b = si.gaussian_source(n, 12)
+    sig, om = rational.kl_first_order(8, 1.0)
+    x = xstar.xstar_dense(A, b, sig, om, R, L, F)
+    # remaining one-dimensional part is handled by g: compare on the split
+    P = R @ L.conj().T
+    ref = signfun.sign_schur(A) @ (P @ b) + xstar.xstar_dense(A, b - P @ b, sig, om)
+    assert rel(x, ref) < 1e-11
+
+
+# ---------------------------------------------------------------- Krylov
+def test_arnoldi_relation_and_hermitian_limit():
+    dims = (2, 2, 2, 4)
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.5, 13)
+    b = si.gaussian_source(12 * V, 14)
+    for mu in (0.3, 0.0):
+        A = dirac.hw_csr(U, dims, 0.25, mu)
+        Vb, H, kk = krylov.arnoldi(lambda v: A @ v, b / np.linalg.norm(b), 15)
+        assert kk == 15
+        assert np.linalg.norm(Vb.conj().T @ Vb - np.eye(16)) < 1e-13
+        assert np.linalg.norm(A @ Vb[:, :15] - Vb @ H) < 1e-13
+        if mu == 0.0:
+            Hk = H[:15, :15]
+            assert np.linalg.norm(np.triu(Hk, 2)) < 1e-12      # tridiagonal
+            assert np.linalg.norm(Hk - Hk.conj().T) < 1e-12
+        else:
+            assert np.linalg.norm(np.triu(H[:15, :15], 2)) > 1e-3
+
+
+def test_plane_wave_breaks_down_at_step_two():
+    """Free field: H(p)^2 = lam^2, so K(H, e^{ipx} chi) has dimension 2."""
+    dims = (4, 4, 4, 4)
+    V = si.lattice_volume(dims)
+    n = 12 * V
+    A = dirac.hw_csr(si.unit_links(dims), dims, 0.25, 0.3)
+    chi = si.gaussian_source(12, 15).reshape(4, 3)
+    # momentum p = (2pi/4, 0, 2pi*2/4, pi/4 + 2pi/4) with antiperiodic time
+    Lx, Ly, Lz, Lt = dims
+    s = np.arange(V)
+    x, y, z, t = s % Lx, (s // Lx) % Ly, (s // (Lx * Ly)) % Lz, s // (Lx * Ly * Lz)
+    ph = np.exp(1j * (2 * np.pi / 4 * x + np.pi * z + (np.pi / 4 + np.pi / 2) * t))
+    b = (ph[:, None, None] * chi[None]).reshape(-1)
+    Vb, H, kk = krylov.arnoldi(lambda v: A @ v, b / np.linalg.norm(b), 10)
+    assert kk == 2
+    sig, om = rational.kl_first_order(5, 0.7)
+    x_rs, info = krylov.restarted_fom_lr(lambda v: A @ v, b, sig, om, k=10)
+    assert info["converged"] and info["cycles"] == 1
+    ref = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: rational.kl_closed_form(0.7 * l, 5))
+    assert rel(x_rs, ref) < 1e-12
+
+
+@pytest.mark.parametrize("k", [8, 12, 40])
+def test_restarted_fom_converges_to_xstar_any_k(k):
+    dims = (2, 2, 3, 4)
+    V = si.lattice_volume(dims)
+    A = dirac.hw_csr(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    sig, om = rational.kl_first_order(5, 0.9)
+    ref = xstar.xstar_dense(A.toarray(), b, sig, om)
+    x, info = krylov.restarted_fom_lr(lambda v: A @ v, b, sig, om, k=k, tol_update=1e-12)
+    assert info["converged"]
+    assert rel(x, ref) < 1e-10
+    # collinear residuals: true per-shift residuals are rho_i * r
+    x2, info2 = krylov.restarted_fom_lr(lambda v: A @ v, b, sig, om, k=k, max_cycles=2,
+                                         keep_shift_solutions=True)
+    X = info2["X"]
+    res = [b - (A @ X[i] - sig[i] * X[i]) for i in range(len(sig))]
+    r0 = res[0] / np.linalg.norm(res[0])
+    for ri in res[1:]:
+        # the part of r_i off the common direction is rounding-sized
+        off = ri - np.vdot(r0, ri) * r0
+        assert np.linalg.norm(off) < 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(res[0]) > 1e-8 * np.linalg.norm(b)   # not yet converged
+
+
+def test_restarted_fom_short_cycle_divergence_is_reported():
+    """Restarted FOM with k = 5 diverges on this indefinite spectrum (both
+    half-planes occupied): the loop must stop and report non-convergence."""
+    dims = (2, 2, 3, 4)
+    V = si.lattice_volume(dims)
+    A = dirac.hw_csr(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    sig, om = rational.kl_first_order(5, 0.9)
+    with np.errstate(all="ignore"):
+        x, info = krylov.restarted_fom_lr(lambda v: A @ v, b, sig, om, k=5, max_cycles=2000)
+    assert not info["converged"]
+
+
+def test_restarted_fom_lr_with_deflation_matches_xstar():
+    dims = (2, 2, 3, 4)
+    V = si.lattice_volume(dims)
+    Ad = dirac.hw_dense(si.gauge_links(dims, 0.5, 18), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 19)
+    R, L, lam, F = deflation.lr_dense(Ad, 10)
+    sig, om = rational.kl_first_order(8, 0.9)
+    ref = xstar.xstar_dense(Ad, b, sig, om, R, L, F)
+    x, info = krylov.restarted_fom_lr(lambda v: Ad @ v, b, sig, om, k=8, R=R, L=L, F=F,
+                                       tol_update=1e-12)
+    assert info["converged"]
+    assert rel(x, ref) < 1e-10
+
+
+def test_unrestarted_multishift_fom_matches_dense():
+    dims = (2, 2, 3, 4)
+    V = si.lattice_volume(dims)
+    A = dirac.hw_csr(si.gauge_links(dims, 0.5, 20), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 21)
+    sig, om = rational.kl_first_order(8, 0.9)
+    x, X, k = krylov.multishift_fom_unrestarted(lambda v: A @ v, b, sig, om, tol=1e-13)
+    ref, Xref = xstar.xstar_dense(A.toarray(), b, sig, om, return_shifts=True)
+    assert rel(x, ref) < 1e-11
+    assert rel(X, Xref) < 1e-11
