@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of sign(H_W) b by restarted multishift FOM-LR on one MI355X.
+
+One step = one complete solve x ~ sign(H_W) b (Algorithm 1: deflated start,
+restart cycles of k Arnoldi steps with CGS2, shifted Hessenberg solves,
+solution update, projection step) for one synthetic source on the 10^4
+lattice at mu = 0.3, with the inputs resident in device memory.  Prints one
+JSON line:  value = solves per second.
+
+    python bench.py [--steps K] [--warmup W] [--config c3] [--mu 0.3]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--mu", type=float, default=0.3)
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--cpu-cycles", type=int, default=2,
+                    help="restart cycles of the CPU oracle to time (bounded sample)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; the sign(H_W)b solve "
+                                   "shards by source (no communication) -- run one process per "
+                                   "GPU with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+    import skinputs as si
+    from skinputs.configs import CONFIGS
+    from paper_0910_2927_amd import api, _lib
+
+    cfg = CONFIGS[args.config]
+    mu = args.mu
+    precision = args.precision or cfg.precision
+    if precision == "mixed":
+        precision_run = "fp64"   # complex-float path not available yet: measured in FP64
+    else:
+        precision_run = precision
+    dev = torch.device("cuda:0")
+    log(f"config {cfg.name} dims={cfg.dims} mu={mu} k={cfg.k} s={cfg.s} precision={precision_run}")
+
+    # ---- inputs (seeded, synthetic), moved to HBM before timing
+    U = si.gauge_links(cfg.dims, cfg.eps, si.seed_for(cfg.L, "gauge"))
+    b = si.gaussian_source(cfg.n, si.seed_for(cfg.L, "b"))
+    links = torch.from_numpy(si.links_soa_from_canonical(U).reshape(-1)).to(dev)
+    bd = torch.from_numpy(si.soa_from_canonical(b, cfg.V)).to(dev)
+    op = api.WilsonOperator(links, cfg.dims, cfg.kappa, mu, cfg.antiperiodic_t)
+    c = cfg.scales.get(mu)
+    if c is None:
+        raise SystemExit(f"no pole scale recorded for {cfg.name} at mu={mu}")
+    sigma, omega = api.kl_poles(cfg.s, c)
+    m_used = 0   # deflation eigensolver on the GPU pending in this build
+    solver = api.SignSolver(op, sigma, omega, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles,
+                            precision=precision_run)
+    x = torch.empty_like(bd)
+
+    # ---- warmup, then K timed solves
+    for _ in range(args.warmup):
+        res = solver(bd, x)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    cycles = []
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        res = solver(bd, x)
+        cycles.append(res.cycles)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    sec = max(ms_total / 1e3, 1e-12)
+    value = args.steps / sec
+    log(f"{args.steps} solves in {sec:.4f} s (wall {wall:.4f} s); cycles/solve={cycles[-1]} "
+        f"matvecs={res.matvecs}")
+
+    # ---- per-kernel timing of one more solve (HIP events on the solve's stream)
+    times = _lib.SkKernelTimes()
+    st = _lib.SkStats()
+    st.times = C.pointer(times)
+    lib = _lib.load()
+    status = lib.sign_apply(C.byref(solver.opstruct), C.byref(solver.params), C.c_void_p(bd.data_ptr()),
+                            C.c_void_p(x.data_ptr()), C.byref(st), C.c_void_p(solver.ws.data_ptr()),
+                            solver.ws.numel(), C.c_void_p(stream.cuda_stream))
+    _lib.check(status)
+    torch.cuda.synchronize()
+    kern = {}
+    for i, name in enumerate(_lib.SK_KERNEL_CLASSES):
+        if times.launches[i]:
+            kern[name] = {"ms": times.ms[i], "launches": int(times.launches[i]),
+                          "avg_us": 1e3 * times.ms[i] / times.launches[i],
+                          "GBs": times.bytes[i] / (times.ms[i] * 1e-3) / 1e9 if times.ms[i] > 0 else None}
+    dom = max(kern, key=lambda k_: kern[k_]["ms"])
+    dom_i = _lib.SK_KERNEL_CLASSES.index(dom)
+    achieved = times.bytes[dom_i] / (times.ms[dom_i] * 1e-3) / 1e9
+    log("kernel classes: " + ", ".join(f"{k_}: {v['ms']:.2f} ms/{v['launches']} "
+                                       f"({v['GBs'] or 0:.0f} GB/s)" for k_, v in kern.items()))
+
+    # ---- parity against the oracle's stored sample, when one exists for this setup
+    err = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_mu{mu:g}.json")
+    if os.path.exists(gpath):
+        g = json.load(open(gpath))
+        if abs(g["c"] - c) == 0 and m_used == cfg.m:
+            xs = si.canonical_from_soa(x.cpu().numpy(), cfg.V)[np.array(g["sample_index"])]
+            ref = np.array(g["x_re"]) + 1j * np.array(g["x_im"])
+            err = float(np.linalg.norm(xs - ref) / np.linalg.norm(ref))
+
+    # ---- CPU baseline: the oracle's restarted FOM-LR, a bounded number of cycles
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import dirac, krylov
+        A = dirac.hw_csr(U, cfg.dims, cfg.kappa, mu, cfg.antiperiodic_t)
+        nc = max(1, args.cpu_cycles)
+        t0 = time.perf_counter()
+        krylov.restarted_fom_lr(lambda v: A @ v, b, sigma, omega, cfg.k, tol_update=cfg.tol,
+                                max_cycles=nc)
+        tc = (time.perf_counter() - t0) / nc
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": 1.0 / (tc * cycles[-1]), "unit": "solves/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{nc} restart cycles (k={cfg.k}) of the oracle's restarted FOM "
+                         f"(CSR matvec, numpy CGS2) on the same 10^4 input, "
+                         f"{tc:.2f} s/cycle, scaled by the {cycles[-1]} cycles a solve takes"}
+        log(f"cpu oracle: {tc:.2f} s per cycle on {cores} cores")
+
+    out = {
+        "metric": "sign(H_W)b solves/s at 10^4, mu=0.3, rel err 1e-8; stencil HBM GB/s",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128" if precision_run == "fp64" else "c64+f64", "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.dims[0]}^4 lattice, eps={cfg.eps}, mu={mu}, "
+                               f"{2 * cfg.s} poles (c={c}), k={cfg.k}, deflation m={m_used}",
+                   "n": cfg.n, "k": cfg.k, "npoles": 2 * cfg.s, "m": m_used,
+                   "precision": precision_run, "cycles_per_solve": cycles[-1],
+                   "matvecs_per_solve": res.matvecs, "sampled_rel_err_vs_oracle": err},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "kernels": kern,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * libsignkrylov -- sign(H_W) b for the non-Hermitian Wilson kernel
+ * H_W = gamma5 D_W(mu) by restarted multishift FOM with LR deflation
+ * (Bloch, Breu, Frommer, Heybrock, Schaefer, Wettig, "Krylov subspace
+ * methods and the sign function: multishifts and deflation in the
+ * non-Hermitian case", Lattice 2009; Algorithm 1, restarted FOM-LR(m,k)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All vector, matrix and link buffers are DEVICE memory owned by the
+ *   caller.  The library never frees them and allocates no device memory
+ *   itself; scratch space is the caller's `ws` workspace, sized by the
+ *   matching *_workspace_bytes query.  Small parameter arrays marked
+ *   "host" are read before the call returns.
+ * - Every call is ordered on `stream` (0 = the null stream).  Calls that
+ *   report results on the host (k_done, sk_stats) synchronise `stream`.
+ * - Complex numbers are interleaved (re, im): 16 bytes for SK_C128
+ *   (double), 8 bytes for SK_C64 (float).
+ * - Lattice: dims = (Lx, Ly, Lz, Lt), V = Lx*Ly*Lz*Lt, site index
+ *   s = ((t*Lz + z)*Ly + y)*Lx + x; direction 0..3 = x, y, z, t.
+ *   Spinor fields are component-major: element (c, s) at c*V + s with
+ *   c = 3*spin + colour (12 components), n = 12 V.  Links are
+ *   [4][3][3][V]: U_nu(x)_{ab} at ((nu*3 + a)*3 + b)*V + s.
+ * - The operator (paper Sect. 1, defined there by reference) is
+ *     D_W(mu) psi(x) = psi(x) - kappa sum_nu [ e^{+mu d_nu,t} (1 - gamma_nu) U_nu(x) psi(x+nu)
+ *                                         + e^{-mu d_nu,t} (1 + gamma_nu) U_nu(x-nu)^+ psi(x-nu) ],
+ *   H_W = gamma5 D_W, chiral basis (gamma5 = diag(1,1,-1,-1)),
+ *   periodic in space, antiperiodic in time when t_antiperiodic != 0.
+ *   H_W(mu)^H = H_W(-mu).
+ * - Return value: SK_OK (0) or a negative sk_status.  Arguments are
+ *   checked on the host before any launch; on error nothing is launched
+ *   and sk_last_error() returns a message (thread-local).  No exception
+ *   crosses this interface.
+ */
+#ifndef SIGNKRYLOV_H
+#define SIGNKRYLOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SK_OK = 0,
+  SK_ERR_ARG = -1,       /* invalid argument: sizes, null pointers, aliasing */
+  SK_ERR_HIP = -2,       /* a HIP runtime call failed */
+  SK_ERR_NOCONV = -3,    /* max_cycles reached; x holds the last iterate */
+  SK_ERR_SINGULAR = -4,  /* H_k - sigma_i singular: FOM iterate undefined */
+  SK_ERR_NAN = -5,       /* non-finite value in the input or the iteration */
+  SK_ERR_WORKSPACE = -6  /* workspace smaller than the query returned */
+} sk_status;
+
+typedef enum {
+  SK_C128 = 0,   /* complex double storage and arithmetic */
+  SK_C64 = 1     /* complex float storage; reductions accumulate in double */
+} sk_dtype;
+
+typedef enum {
+  SK_PREC_FP64 = 0,   /* every vector in complex double */
+  SK_PREC_MIXED = 1   /* complex-float basis and stencil, double refinement */
+} sk_precision;
+
+typedef struct {
+  int32_t dims[4];          /* Lx, Ly, Lz, Lt, each >= 1 */
+  int32_t t_antiperiodic;   /* 1: antiperiodic time boundary, 0: periodic */
+  double kappa;             /* hopping parameter, 1/(2 m_W + 8) */
+  double mu;                /* quark chemical potential (time hops) */
+  const void* links;        /* device, complex double [4][3][3][V] */
+  const void* links_c64;    /* device, complex float copy; needed by SK_C64 calls */
+} sk_operator;
+
+/*
+ * Poles and weights of the Kenney-Laub rational approximation of sign
+ * (Sect. 6): g_s(c t) = c t sum_{i=1..s} w_i / (c^2 t^2 + tau_i^2),
+ * theta_i = pi (i - 1/2) / (2 s), tau_i = tan(theta_i), w_i = 1/(s cos^2 theta_i),
+ * split into N = 2 s first-order terms of eq. (g):
+ *   sigma_{2i} = +i tau_i / c,  sigma_{2i+1} = -i tau_i / c,  omega = w_i / (2 c).
+ * sigma, omega: host, 2 s complex (re, im interleaved) each.  s in [1, 32], c > 0.
+ */
+int kl_poles(int s, double c, double* sigma, double* omega);
+
+/* Number of lattice sites of an operator (0 if dims are invalid). */
+int64_t sk_volume(const sk_operator* op);
+
+/* Thread-local message for the last failing call on this thread. */
+const char* sk_last_error(void);
+
+/*
+ * w = H_W v  (adjoint = 0)  or  w = H_W^H v = H_W(-mu) v  (adjoint = 1).
+ * The matrix-vector product every Krylov step needs (Sect. 2: Krylov
+ * methods touch A only through products with vectors).
+ * in, out: device, n = 12 V complex of `dtype`; must not overlap.
+ */
+int wilson_apply(const sk_operator* op, sk_dtype dtype, const void* in, void* out,
+                 int adjoint, hipStream_t stream);
+
+/*
+ * One cycle of k Arnoldi steps (Sect. 2, Arnoldi relation
+ * A V_k = V_k H_k + h_{k+1,k} v_{k+1} e_k^T), with classical Gram-Schmidt
+ * applied twice per step (CGS2).
+ *   V:  device, (k+1) vectors of n complex `dtype`, vector j at V + j*n.
+ *       On entry V[0] holds a nonzero start vector (it is normalised);
+ *       on exit V[0..k_done] are orthonormal.
+ *   H:  device, complex double, (k+1) x k column-major (ld = k+1);
+ *       entries below the subdiagonal are zero.
+ *   k_done: host out; k, or the step j < k at which h_{j+1,j} fell below
+ *       1e-12 ||A v_j|| (lucky breakdown: K_j is invariant).
+ *   ws: device workspace of arnoldi_cycle_workspace_bytes(op, k) bytes.
+ * Synchronises `stream` (k_done is read back).
+ */
+size_t arnoldi_cycle_workspace_bytes(const sk_operator* op, int k);
+int arnoldi_cycle(const sk_operator* op, sk_dtype dtype, void* V, double* H, int k,
+                  int* k_done, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The per-cycle multishift FOM step of Algorithm 1 (Sect. 3 and 5):
+ *   y_i  = beta rho_i (H_k - sigma_i I)^{-1} e_1,  i = 1..npoles  (double)
+ *   x   += V_k sum_i omega_i y_i
+ *   X_i += V_k y_i                      (only if X_shift != NULL)
+ *   rho_i <- -h_{k+1,k} e_k^T y_i       (collinear residuals r_i = rho_i v_{k+1})
+ *   H, beta, rho: device, complex double (H as in arnoldi_cycle, ld = k+1;
+ *        beta is one real double; rho has npoles complex entries, in/out).
+ *   sigma, omega: host, npoles complex double each (re, im interleaved).
+ *   V: device, k orthonormal vectors of `dtype` (vector j at V + j*n).
+ *   x, X_shift: device complex double, n and npoles*n entries.
+ *   upd_norm: host double out, ||sum_i omega_i y_i||_2.
+ *   ws: device workspace of multishift_fom_restart_workspace_bytes(k, npoles).
+ * Returns SK_ERR_SINGULAR if some H_k - sigma_i had a zero pivot.
+ * Synchronises `stream`.
+ */
+size_t multishift_fom_restart_workspace_bytes(int k, int npoles);
+int multishift_fom_restart(int k, int64_t n, sk_dtype dtype, const double* H,
+                           int npoles, const double* sigma, const double* omega,
+                           const double* beta, double* rho, const void* V, double* x,
+                           double* X_shift, double* upd_norm, void* ws, size_t ws_bytes,
+                           hipStream_t stream);
+
+/*
+ * LR deflation (Sect. 4): with P = R L^H (L^H R = I_m),
+ *   coeff = L^H in                         (device, m complex double)
+ *   r_out = (I - P) in
+ *   xp_out = R F coeff   (if xp_out and F are non-NULL; F = f(Lambda) in
+ *                         the basis R, m x m complex double column-major,
+ *                         device; diagonal sign(Re lambda) for LR vectors)
+ * R, L: device complex double, m vectors of n entries (vector i at +i*n).
+ * in, r_out, xp_out: device complex double, n entries; r_out may equal in,
+ * xp_out must not overlap either.
+ * ws: device workspace of deflate_project_workspace_bytes(m, n).
+ */
+size_t deflate_project_workspace_bytes(int m, int64_t n);
+int deflate_project(int m, int64_t n, const double* R, const double* L, const double* F,
+                    const double* in, double* r_out, double* xp_out, double* coeff,
+                    void* ws, size_t ws_bytes, hipStream_t stream);
+
+typedef struct {
+  int32_t npoles;           /* N first-order poles of eq. (g) */
+  const double* sigma;      /* host, N complex (re, im) */
+  const double* omega;      /* host, N complex (re, im) */
+  int32_t k;                /* restart length k_max (1 <= k <= 256) */
+  int32_t max_cycles;       /* cap on restart cycles */
+  double tol;               /* stop when ||update|| <= tol*||x|| twice in a row */
+  int32_t m;                /* deflation dimension (0: none) */
+  const double* R;          /* device, m x n complex double (right vectors) */
+  const double* L;          /* device, m x n complex double (left vectors, L^H R = I) */
+  const double* F;          /* device, m x m complex double, f(Lambda) in basis R */
+  int32_t project_each_cycle; /* 1: projection step after every cycle (Alg. 1) */
+  int32_t precision;        /* sk_precision */
+  double* X_shift;          /* device, N x n complex double, or NULL: per-shift
+                               solutions of (A - sigma_i) X_i = (I - P) b */
+} sk_sign_params;
+
+/* Kernel classes of a solve, for the optional per-kernel timing. */
+typedef enum {
+  SK_K_STENCIL = 0,     /* w = H_W v */
+  SK_K_GS_DOT = 1,      /* Gram-Schmidt pass 1: h = V^H w */
+  SK_K_GS_UPD_DOT = 2,  /* w -= V h, then pass 2 dots V^H w */
+  SK_K_GS_UPD_NORM = 3, /* w -= V h2, then ||w|| */
+  SK_K_SMALL = 4,       /* shifted Hessenberg solves */
+  SK_K_SOL_UPDATE = 5,  /* x += V_k u (and per-shift X) */
+  SK_K_PROJECT = 6,     /* deflation projection / restart vector */
+  SK_K_COUNT = 7
+} sk_kernel_class;
+
+/* Per-class kernel time (HIP events on the call's stream, summed over the
+   solve) and algorithmic bytes: the bytes the operation must move at
+   minimum (each operand read once, each result written once). */
+typedef struct {
+  double ms[8];
+  double bytes[8];
+  int64_t launches[8];
+} sk_kernel_times;
+
+typedef struct {
+  int32_t cycles;           /* restart cycles run */
+  int32_t matvecs;          /* H_W applications (all precisions) */
+  int32_t converged;        /* 1 if the stopping rule was met */
+  int32_t breakdown;        /* 1 if a cycle ended in lucky breakdown */
+  double final_update_norm; /* ||sum omega_i y_i|| of the last cycle */
+  double x_norm;            /* ||x|| at exit */
+  double* hist_update;      /* host, nullable: per-cycle update norms */
+  double* hist_beta;        /* host, nullable: per-cycle ||r|| */
+  double* hist_leak;        /* host, nullable: per-cycle ||L^H r|| before projection */
+  int32_t hist_cap;         /* capacity of the history arrays */
+  sk_kernel_times* times;   /* host, nullable: if set, every kernel of the solve
+                               is bracketed by HIP events (slightly slower) */
+} sk_stats;
+
+/*
+ * x = sign(H_W) b approximated by Algorithm 1 (restarted FOM-LR(m,k)):
+ *   x = R F L^H b + sum_i omega_i x_i,  (H_W - sigma_i) x_i = (I - R L^H) b,
+ * to the stopping rule above.  b, x: device complex double, n entries,
+ * no overlap.  stats: host, nullable.  One host read-back per cycle.
+ * Returns SK_ERR_NOCONV if max_cycles ran out (x holds the iterate).
+ */
+size_t sign_apply_workspace_bytes(const sk_operator* op, const sk_sign_params* p);
+int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, double* x,
+               sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIGNKRYLOV_H */

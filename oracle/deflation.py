@@ -59,18 +59,26 @@ def lr_dense(A, m, key="abs"):
 def _arpack_sq(A, m, extra, tol):
     n = A.shape[0]
     op = spla.LinearOperator((n, n), matvec=lambda v: A @ (A @ v), dtype=np.complex128)
-    _, vec = spla.eigs(op, k=m + extra, which="SR", ncv=min(n - 1, 3 * (m + extra) + 20),
-                       tol=tol, maxiter=200000)
+    mu2, vec = spla.eigs(op, k=m + extra, which="SR", ncv=min(n - 1, 3 * (m + extra) + 20),
+                         tol=tol, maxiter=200000)
     vec = vec / np.linalg.norm(vec, axis=0)
     lam = np.array([vec[:, i].conj() @ (A @ vec[:, i]) for i in range(vec.shape[1])])
-    return lam, vec
+    return lam, vec, mu2
 
 
-def lr_arpack(A, AH, m, key="abs", extra=6, tol=1e-13):
-    """(R, L, Lambda, F) for a sparse A with AH = A^H, via ARPACK on A^2."""
-    lam_r, Rr = _arpack_sq(A, m, extra, tol)
-    lam_l, Ll = _arpack_sq(AH, m, extra, tol)
+def lr_arpack(A, AH, m, key="abs", extra=6, tol=1e-13, return_all=False):
+    """(R, L, Lambda, F) for a sparse A with AH = A^H, via ARPACK on A^2.
+
+    Completeness: every eigenvalue of A with |lambda| <= |lambda_(m)| has
+    Re(lambda^2) <= |lambda|^2, so it is among the computed ones as long as
+    the largest computed Re(lambda^2) is at least |lambda_(m)|^2 -- checked.
+    (Same argument with |Re lambda| for key="re".)"""
+    lam_r, Rr, mu2 = _arpack_sq(A, m, extra, tol)
+    lam_l, Ll, _ = _arpack_sq(AH, m, extra, tol)
     sel, _ = select_critical(lam_r, m, key)
+    kv = np.abs(lam_r[sel]) if key == "abs" else np.abs(lam_r[sel].real)
+    if np.max(mu2.real) < np.max(kv) ** 2:
+        raise RuntimeError("ARPACK window too small to certify the selection")
     R = Rr[:, sel]
     lam = lam_r[sel]
     L = np.empty_like(R)
@@ -81,6 +89,8 @@ def lr_arpack(A, AH, m, key="abs", extra=6, tol=1e-13):
         L[:, i] = Ll[:, j]
     M = L.conj().T @ R
     L = L @ np.linalg.inv(M).conj().T
+    if return_all:
+        return R, L, lam, sign_f_diag(lam), lam_r
     return R, L, lam, sign_f_diag(lam)
 
 

@@ -16,7 +16,8 @@ TEST INFRASTRUCTURE ONLY.
   on two consecutive cycles, or on Arnoldi breakdown (exact result).
   Restarted FOM is not monotone: for a short cycle on a spectrum on both
   sides of the imaginary axis, H_k - sigma_i can be nearly singular and the
-  iterates blow up; a non-finite update ends the loop unconverged.
+  iterates blow up; a non-finite update, or one 1e10 times the first,
+  ends the loop unconverged.
 * ``multishift_fom_unrestarted``: one long Arnoldi run with the FOM iterate
   of every shift, for large n where dense solves are out of reach.
 """
@@ -122,6 +123,8 @@ def restarted_fom_lr(matvec, b, sigma, omega, k, R=None, L=None, F=None,
         upd_hist.append(un)
         if not np.isfinite(un) or not np.all(np.isfinite(rho)):
             break                           # diverged: restarted FOM is not monotone
+        if cycles > 1 and un > 1e10 * upd_hist[0]:
+            break                           # same divergence, caught before overflow
         if history is not None:
             history.append({"beta": beta, "rho": rho.copy(), "h_next": H[kk, kk - 1],
                             "update": un, "H": H.copy(), "kk": kk})

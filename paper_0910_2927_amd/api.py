@@ -1,0 +1,238 @@
+"""Thin Python binding of libsignkrylov over torch device tensors.
+
+Only argument marshalling lives here: torch provides device memory
+(tensors, the workspace) and the current stream; every step of the
+computation runs in the library's HIP kernels.  Field layout is the
+library's: complex tensors of shape (12, V) (component-major, site fastest)
+and links of shape (4, 3, 3, V).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["WilsonOperator", "SignResult", "kl_poles", "wilson_apply", "arnoldi_cycle",
+           "multishift_fom_restart", "deflate_project", "sign_apply", "SkError"]
+
+SkError = L.SkError
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _need(t, dtype, numel=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _cplx_host(arr):
+    a = np.ascontiguousarray(np.asarray(arr, dtype=np.complex128))
+    buf = (C.c_double * (2 * a.size))(*a.view(np.float64))
+    return buf, a.size
+
+
+class WilsonOperator:
+    """H_W = gamma5 D_W(mu) on a lattice with device-resident links.
+
+    links: complex128 CUDA tensor (4, 3, 3, V); links64 (optional) the
+    complex64 copy used by complex-float calls."""
+
+    def __init__(self, links, dims, kappa, mu, antiperiodic_t=True, links64=None):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.n = 12 * self.V
+        _need(links, torch.complex128, 36 * self.V, "links")
+        if links64 is not None:
+            _need(links64, torch.complex64, 36 * self.V, "links64")
+        self.links = links
+        self.links64 = links64
+        self.kappa = float(kappa)
+        self.mu = float(mu)
+        self.antiperiodic_t = bool(antiperiodic_t)
+        self.device = links.device
+
+    def struct(self, mu=None):
+        s = L.SkOperator()
+        for i in range(4):
+            s.dims[i] = self.dims[i]
+        s.t_antiperiodic = 1 if self.antiperiodic_t else 0
+        s.kappa = self.kappa
+        s.mu = self.mu if mu is None else float(mu)
+        s.links = self.links.data_ptr()
+        s.links_c64 = self.links64.data_ptr() if self.links64 is not None else None
+        return s
+
+    def with_mu(self, mu):
+        return WilsonOperator(self.links, self.dims, self.kappa, mu, self.antiperiodic_t, self.links64)
+
+
+def kl_poles(s, c):
+    """First-order poles/weights of the Kenney-Laub g_s(c x) (library routine)."""
+    lib = L.load()
+    sg = (C.c_double * (4 * s))()
+    om = (C.c_double * (4 * s))()
+    L.check(lib.kl_poles(int(s), float(c), sg, om))
+    a = np.frombuffer(sg, dtype=np.float64).copy().view(np.complex128)
+    b = np.frombuffer(om, dtype=np.float64).copy().view(np.complex128)
+    return a, b
+
+
+def wilson_apply(op: WilsonOperator, v, adjoint=False, out=None):
+    lib = L.load()
+    dt = L.SK_C128 if v.dtype == torch.complex128 else L.SK_C64
+    _need(v, v.dtype, op.n, "v")
+    if out is None:
+        out = torch.empty_like(v)
+    s = op.struct()
+    L.check(lib.wilson_apply(C.byref(s), dt, _ptr(v), _ptr(out), 1 if adjoint else 0, _stream()))
+    return out
+
+
+def arnoldi_cycle(op: WilsonOperator, v0, k):
+    """Returns (V (k+1, n), H (k+1, k) complex128, k_done)."""
+    lib = L.load()
+    dt = L.SK_C128 if v0.dtype == torch.complex128 else L.SK_C64
+    _need(v0, v0.dtype, op.n, "v0")
+    V = torch.empty((k + 1, op.n), dtype=v0.dtype, device=v0.device)
+    V[0].copy_(v0.reshape(-1))
+    H = torch.empty((k, k + 1), dtype=torch.complex128, device=v0.device)  # column-major (k+1) x k
+    s = op.struct()
+    ws = _workspace(lib.arnoldi_cycle_workspace_bytes(C.byref(s), k), v0.device)
+    kd = C.c_int(0)
+    L.check(lib.arnoldi_cycle(C.byref(s), dt, _ptr(V), _ptr(H), k, C.byref(kd), _ptr(ws),
+                              ws.numel(), _stream()))
+    return V, H.transpose(0, 1), kd.value
+
+
+def multishift_fom_restart(H, k, sigma, omega, beta, rho, V, x, X_shift=None):
+    """One multishift FOM update (in place on rho, x, X_shift); returns ||u||."""
+    lib = L.load()
+    sg, N = _cplx_host(sigma)
+    om, _ = _cplx_host(omega)
+    dt = L.SK_C128 if V.dtype == torch.complex128 else L.SK_C64
+    n = x.numel()
+    Hc = H.transpose(0, 1).contiguous()   # column-major storage
+    ws = _workspace(lib.multishift_fom_restart_workspace_bytes(k, N), x.device)
+    upd = C.c_double(0.0)
+    L.check(lib.multishift_fom_restart(k, n, dt, _ptr(Hc), N, sg, om, _ptr(beta), _ptr(rho),
+                                       _ptr(V), _ptr(x), _ptr(X_shift), C.byref(upd), _ptr(ws),
+                                       ws.numel(), _stream()))
+    return upd.value
+
+
+def deflate_project(R, Lv, v, F=None):
+    """Returns (r = (I - R L^H) v, coeff = L^H v, x_P = R F coeff or None)."""
+    lib = L.load()
+    m, n = R.shape
+    r = torch.empty_like(v)
+    coeff = torch.empty(m, dtype=torch.complex128, device=v.device)
+    xp = torch.empty_like(v) if F is not None else None
+    Fc = F.transpose(0, 1).contiguous() if F is not None else None
+    ws = _workspace(lib.deflate_project_workspace_bytes(m, n), v.device)
+    L.check(lib.deflate_project(m, n, _ptr(R), _ptr(Lv), _ptr(Fc), _ptr(v), _ptr(r), _ptr(xp),
+                                _ptr(coeff), _ptr(ws), ws.numel(), _stream()))
+    return r, coeff, xp
+
+
+@dataclass
+class SignResult:
+    x: torch.Tensor
+    status: int
+    cycles: int
+    matvecs: int
+    converged: bool
+    breakdown: bool
+    update_norms: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    betas: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    leaks: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    X_shift: torch.Tensor | None = None
+
+
+class SignSolver:
+    """Holds the parameters and workspace of repeated sign_apply calls."""
+
+    def __init__(self, op: WilsonOperator, sigma, omega, k, tol=1e-9, max_cycles=500,
+                 R=None, Lv=None, F=None, project_each_cycle=True, precision="fp64",
+                 keep_shift_solutions=False, hist_cap=4096):
+        self.lib = L.load()
+        self.op = op
+        self._sg, self.N = _cplx_host(sigma)
+        self._om, _ = _cplx_host(omega)
+        self.k = int(k)
+        self.m = 0 if R is None else int(R.shape[0])
+        if self.m:
+            _need(R, torch.complex128, self.m * op.n, "R")
+            _need(Lv, torch.complex128, self.m * op.n, "L")
+            F = F.transpose(0, 1).contiguous()   # column-major
+            _need(F, torch.complex128, self.m * self.m, "F")
+        self.R, self.Lv, self.F = R, Lv, F
+        self.X = (torch.empty((self.N, op.n), dtype=torch.complex128, device=op.device)
+                  if keep_shift_solutions else None)
+        p = L.SkSignParams()
+        p.npoles = self.N
+        p.sigma = C.cast(self._sg, C.POINTER(C.c_double))
+        p.omega = C.cast(self._om, C.POINTER(C.c_double))
+        p.k = self.k
+        p.max_cycles = int(max_cycles)
+        p.tol = float(tol)
+        p.m = self.m
+        p.R = R.data_ptr() if self.m else None
+        p.L = Lv.data_ptr() if self.m else None
+        p.F = self.F.data_ptr() if self.m else None
+        p.project_each_cycle = 1 if project_each_cycle else 0
+        p.precision = L.SK_PREC_MIXED if precision == "mixed" else L.SK_PREC_FP64
+        p.X_shift = self.X.data_ptr() if self.X is not None else None
+        self.params = p
+        self.opstruct = op.struct()
+        nb = self.lib.sign_apply_workspace_bytes(C.byref(self.opstruct), C.byref(p))
+        if nb == 0:
+            raise SkError(L.SK_ERR_ARG, "invalid parameters for sign_apply")
+        self.ws = _workspace(nb, op.device)
+        self.hist_cap = hist_cap
+        self._hu = (C.c_double * hist_cap)()
+        self._hb = (C.c_double * hist_cap)()
+        self._hl = (C.c_double * hist_cap)()
+
+    def __call__(self, b, x=None, raise_on_error=True):
+        _need(b, torch.complex128, self.op.n, "b")
+        if x is None:
+            x = torch.empty_like(b)
+        st = L.SkStats()
+        st.hist_update = C.cast(self._hu, C.POINTER(C.c_double))
+        st.hist_beta = C.cast(self._hb, C.POINTER(C.c_double))
+        st.hist_leak = C.cast(self._hl, C.POINTER(C.c_double))
+        st.hist_cap = self.hist_cap
+        status = self.lib.sign_apply(C.byref(self.opstruct), C.byref(self.params), _ptr(b), _ptr(x),
+                                     C.byref(st), _ptr(self.ws), self.ws.numel(), _stream())
+        if raise_on_error and status not in (L.SK_OK,):
+            L.check(status)
+        nc = min(st.cycles, self.hist_cap)
+        return SignResult(x=x, status=status, cycles=st.cycles, matvecs=st.matvecs,
+                          converged=bool(st.converged), breakdown=bool(st.breakdown),
+                          update_norms=np.array(self._hu[:nc]), betas=np.array(self._hb[:nc]),
+                          leaks=np.array(self._hl[:nc]), X_shift=self.X)
+
+
+def sign_apply(op, b, sigma, omega, k, **kw):
+    return SignSolver(op, sigma, omega, k, **{k_: v for k_, v in kw.items() if k_ != "raise_on_error"})(
+        b, raise_on_error=kw.get("raise_on_error", True))

@@ -1,0 +1,759 @@
+// Host side of libsignkrylov: argument checks, workspace layout, and the
+// restart loop of Algorithm 1 (restarted FOM-LR(m,k)) built from the
+// kernels in wilson.hip, tsla.hip and small.hip.
+#include "sk_internal.h"
+
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+namespace sk {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+int check_operator(const sk_operator* op, sk_dtype dtype) {
+  SK_CHECK(op != nullptr, "operator is NULL");
+  for (int i = 0; i < 4; ++i) SK_CHECK(op->dims[i] >= 1, "dims[%d] = %d must be >= 1", i, op->dims[i]);
+  const int64_t V = volume_of(op);
+  SK_CHECK(V * 12 < (int64_t(1) << 31), "lattice too large (V = %lld)", (long long)V);
+  SK_CHECK(std::isfinite(op->kappa) && std::isfinite(op->mu), "kappa and mu must be finite");
+  SK_CHECK(dtype == SK_C128 || dtype == SK_C64, "unknown dtype %d", (int)dtype);
+  if (dtype == SK_C128) SK_CHECK(op->links != nullptr, "links (complex double) are NULL");
+  else SK_CHECK(op->links_c64 != nullptr, "links_c64 are NULL but a complex-float call was made");
+  return SK_OK;
+}
+
+namespace {
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+// Carves the caller's workspace into aligned pieces.
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T> T* take(size_t count) {
+    size_t o = off;
+    off = align256(off + count * sizeof(T));
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+// Device scratch used by an Arnoldi-based driver.
+template <typename T>
+struct KrylovWs {
+  T* W;                // (k+1) basis slots, unnormalised: v_j = scale[j] W_j
+  double2* H;
+  double* scale;
+  double* wnorm;
+  double2* coef;
+  double2* partial;
+  unsigned* counter;
+  CycleState* st;
+  double2* rho;
+  double2* Y;
+  double2* U;
+  double2* ucoef;
+  double2* ycoef;
+  double2* dc;
+  double2* dc2;
+};
+
+template <typename T>
+size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int m, bool keep) {
+  const int pmax = k > m ? k : m;
+  w.W = c.template take<T>((size_t)(k + 1) * n);
+  w.H = c.template take<double2>((size_t)(k + 1) * k);
+  w.scale = c.template take<double>(k + 2);
+  w.wnorm = c.template take<double>(k + 1);
+  w.coef = c.template take<double2>(kMaxK + 4);
+  w.partial = c.template take<double2>(ts_partial_entries(n, pmax));
+  w.counter = c.template take<unsigned>(16);
+  w.st = c.template take<CycleState>(1);
+  w.rho = c.template take<double2>(npoles > 0 ? npoles : 1);
+  w.Y = c.template take<double2>((size_t)(npoles > 0 ? npoles : 1) * k);
+  w.U = c.template take<double2>((size_t)(npoles > 0 ? npoles : 1) * k * k);
+  w.ucoef = c.template take<double2>(k + 1);
+  w.ycoef = keep ? c.template take<double2>((size_t)npoles * k) : nullptr;
+  w.dc = c.template take<double2>(m > 0 ? m : 1);
+  w.dc2 = c.template take<double2>(m > 0 ? m : 1);
+  return c.off;
+}
+
+template <typename T>
+ArnoldiDev arn_of(const KrylovWs<T>& w, int k) {
+  ArnoldiDev a;
+  a.H = w.H;
+  a.scale = w.scale;
+  a.wnorm = w.wnorm;
+  a.coef = w.coef;
+  a.partial = w.partial;
+  a.counter = w.counter;
+  a.st = w.st;
+  a.ldh = k + 1;
+  return a;
+}
+
+TsEpiArgs epi_of(int kind, const ArnoldiDev& a, int j = 0) {
+  TsEpiArgs e;
+  std::memset(&e, 0, sizeof(e));
+  e.epi = kind;
+  e.j = j;
+  e.arn = a;
+  return e;
+}
+
+// Optional per-kernel timing: HIP events around every launch of a solve,
+// summed per kernel class after each cycle's host synchronisation.
+struct KTimer {
+  sk_kernel_times* out = nullptr;
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> pool;
+  struct Rec { int cls; double bytes; int e0, e1; };
+  std::vector<Rec> recs;
+  size_t used = 0;
+  int cur_cls = 0, cur_e0 = 0;
+  double cur_bytes = 0.0;
+  bool on() const { return out != nullptr; }
+  int record() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+    hipEventRecord(pool[used], s);
+    return (int)used++;
+  }
+  void begin(int cls, double bytes) {
+    if (!on()) return;
+    cur_cls = cls;
+    cur_bytes = bytes;
+    cur_e0 = record();
+  }
+  void end() {
+    if (!on()) return;
+    int e1 = record();
+    if (cur_e0 >= 0 && e1 >= 0) recs.push_back({cur_cls, cur_bytes, cur_e0, e1});
+  }
+  // call after the stream has been synchronised
+  void flush() {
+    if (!on()) return;
+    for (const Rec& r : recs) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pool[r.e0], pool[r.e1]) == hipSuccess) {
+        out->ms[r.cls] += ms;
+        out->bytes[r.cls] += r.bytes;
+        out->launches[r.cls] += 1;
+      }
+    }
+    recs.clear();
+    used = 0;
+  }
+  ~KTimer() {
+    for (hipEvent_t e : pool) hipEventDestroy(e);
+  }
+};
+
+template <typename T> const T* links_as(const sk_operator* op);
+template <> const double2* links_as<double2>(const sk_operator* op) { return (const double2*)op->links; }
+template <> const float2* links_as<float2>(const sk_operator* op) { return (const float2*)op->links_c64; }
+
+#define SK_LAUNCH(call)                                                                   \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      ::sk::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, \
+                      __LINE__);                                                          \
+      return SK_ERR_HIP;                                                                  \
+    }                                                                                     \
+  } while (0)
+
+// k Arnoldi steps on the unnormalised basis in w.W; W_0 and scale[0] must be
+// set.  Kernels after a breakdown return at once (skip flag).
+template <typename T>
+int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int k, int adjoint,
+                    hipStream_t s, KTimer* tm = nullptr) {
+  const ArnoldiDev a = arn_of(w, k);
+  const T* U = links_as<T>(op);
+  const int* skip = &w.st->breakdown;
+  KTimer dummy;
+  KTimer& t = tm ? *tm : dummy;
+  const double c = (double)sizeof(T), nn = (double)n;
+  for (int j = 0; j < k; ++j) {
+    T* wj1 = w.W + (size_t)(j + 1) * n;
+    // stencil: 12 in + 36 link + 12 out complex per site = 5 n complex
+    t.begin(SK_K_STENCIL, 5.0 * nn * c);
+    SK_LAUNCH((launch_wilson<T, T, T>(op, U, w.W + (size_t)j * n, wj1, adjoint, w.scale + j, skip, s)));
+    t.end();
+    t.begin(SK_K_GS_DOT, (j + 2) * nn * c);
+    SK_LAUNCH((ts_dot<T, T>(w.W, n, j + 1, wj1, n, true, epi_of(EPI_ARN_H1, a, j), w.partial,
+                            w.counter + 0, skip, s)));
+    t.end();
+    t.begin(SK_K_GS_UPD_DOT, (j + 3) * nn * c);
+    SK_LAUNCH((ts_update<T, T, T>(w.W, n, j + 1, w.coef, nullptr, wj1, wj1, n, 1,
+                                  epi_of(EPI_ARN_H2, a, j), w.partial, w.counter + 1, skip, s)));
+    t.end();
+    t.begin(SK_K_GS_UPD_NORM, (j + 3) * nn * c);
+    SK_LAUNCH((ts_update<T, T, T>(w.W, n, j + 1, w.coef, nullptr, wj1, wj1, n, 2,
+                                  epi_of(EPI_ARN_NORM, a, j), w.partial, w.counter + 2, skip, s)));
+    t.end();
+  }
+  return SK_OK;
+}
+
+std::mutex g_mu;
+
+}  // namespace
+}  // namespace sk
+
+using namespace sk;
+
+extern "C" {
+
+const char* sk_last_error(void) { return sk::g_err; }
+
+int kl_poles(int s, double c, double* sigma, double* omega) {
+  SK_CHECK(s >= 1 && 2 * s <= kMaxPoles, "s = %d outside [1, %d]", s, kMaxPoles / 2);
+  SK_CHECK(c > 0.0 && std::isfinite(c), "scale c must be positive");
+  SK_CHECK(sigma && omega, "sigma/omega are NULL");
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < s; ++i) {
+    const double th = pi / (2.0 * s) * (i + 0.5);
+    const double tau = std::tan(th), cs = std::cos(th);
+    const double w = 1.0 / (s * cs * cs);
+    sigma[4 * i + 0] = 0.0;
+    sigma[4 * i + 1] = tau / c;
+    sigma[4 * i + 2] = 0.0;
+    sigma[4 * i + 3] = -tau / c;
+    omega[4 * i + 0] = w / (2.0 * c);
+    omega[4 * i + 1] = 0.0;
+    omega[4 * i + 2] = w / (2.0 * c);
+    omega[4 * i + 3] = 0.0;
+  }
+  return SK_OK;
+}
+
+int64_t sk_volume(const sk_operator* op) { return volume_of(op); }
+
+int wilson_apply(const sk_operator* op, sk_dtype dtype, const void* in, void* out, int adjoint,
+                 hipStream_t stream) {
+  SK_TRY(check_operator(op, dtype));
+  const int64_t n = 12 * volume_of(op);
+  SK_CHECK(in && out, "in/out must be non-NULL");
+  SK_CHECK(!overlap(in, n * cbytes(dtype), out, n * cbytes(dtype)), "in and out overlap");
+  if (dtype == SK_C128)
+    SK_LAUNCH((launch_wilson<double2, double2, double2>(op, (const double2*)op->links, (const double2*)in,
+                                                        (double2*)out, adjoint, nullptr, nullptr, stream)));
+  else
+    SK_LAUNCH((launch_wilson<float2, float2, float2>(op, (const float2*)op->links_c64, (const float2*)in,
+                                                     (float2*)out, adjoint, nullptr, nullptr, stream)));
+  return SK_OK;
+}
+
+// ------------------------------------------------------------------ arnoldi_cycle
+}  // extern "C"
+
+namespace sk {
+// Scratch of arnoldi_cycle: everything but the basis and H, which the caller owns.
+template <typename T>
+static size_t carve_arnoldi(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
+  std::memset(&w, 0, sizeof(w));
+  w.scale = c.template take<double>(k + 2);
+  w.wnorm = c.template take<double>(k + 1);
+  w.coef = c.template take<double2>(kMaxK + 4);
+  w.partial = c.template take<double2>(ts_partial_entries(n, k));
+  w.counter = c.template take<unsigned>(16);
+  w.st = c.template take<CycleState>(1);
+  w.rho = c.template take<double2>(1);
+  return c.off;
+}
+
+}  // namespace sk
+
+extern "C" {
+
+size_t arnoldi_cycle_workspace_bytes(const sk_operator* op, int k) {
+  if (!op || k < 1 || k > kMaxK || volume_of(op) <= 0) return 0;
+  Carver c;
+  KrylovWs<double2> w;
+  return carve_arnoldi(c, w, 12 * volume_of(op), k);
+}
+
+}  // extern "C"
+
+namespace sk {
+template <typename T>
+static int arnoldi_impl(const sk_operator* op, T* V, double2* H, int k, int* k_done, void* ws,
+                        hipStream_t s) {
+  const int64_t n = 12 * volume_of(op);
+  Carver c;
+  c.base = (char*)ws;
+  KrylovWs<T> w;
+  carve_arnoldi(c, w, n, k);
+  w.W = V;
+  w.H = H;
+  const ArnoldiDev a = arn_of(w, k);
+  SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, 16, s));
+  SK_LAUNCH(launch_fill_zero((double*)H, (int64_t)(k + 1) * k * 2, s));
+  // normalise the start vector: scale[0] = 1/||V_0||
+  TsEpiArgs eb = epi_of(EPI_BETA, a);
+  eb.dst_scalar = &w.st->beta;
+  eb.dst_scale = w.scale;
+  SK_LAUNCH((ts_dot<T, T>(V, n, 0, V, n, true, eb, w.partial, w.counter + 3, nullptr, s)));
+  SK_TRY(enqueue_arnoldi<T>(op, w, n, k, 0, s));
+  SK_LAUNCH((ts_scale_basis<T>(V, n, k + 1, w.scale, &w.st->kdone, n, s)));
+  CycleState hs;
+  SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  SK_HIP(hipStreamSynchronize(s));
+  if (!(hs.beta > 0.0) || !std::isfinite(hs.beta)) {
+    set_error("start vector is zero or not finite");
+    return hs.beta > 0.0 ? SK_ERR_NAN : SK_ERR_ARG;
+  }
+  if (hs.nonfinite) {
+    set_error("non-finite value in the Arnoldi process");
+    return SK_ERR_NAN;
+  }
+  if (k_done) *k_done = hs.kdone;
+  return SK_OK;
+}
+
+}  // namespace sk
+
+extern "C" {
+
+int arnoldi_cycle(const sk_operator* op, sk_dtype dtype, void* V, double* H, int k, int* k_done,
+                  void* ws, size_t ws_bytes, hipStream_t stream) {
+  SK_TRY(check_operator(op, dtype));
+  SK_CHECK(k >= 1 && k <= kMaxK, "k = %d outside [1, %d]", k, kMaxK);
+  SK_CHECK(V && H && ws, "V, H and ws must be non-NULL");
+  const int64_t n = 12 * volume_of(op);
+  const size_t need = arnoldi_cycle_workspace_bytes(op, k);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  SK_CHECK(!overlap(V, (size_t)(k + 1) * n * cbytes(dtype), H, (size_t)(k + 1) * k * 16),
+           "V and H overlap");
+  if (dtype == SK_C128) return arnoldi_impl<double2>(op, (double2*)V, (double2*)H, k, k_done, ws, stream);
+  return arnoldi_impl<float2>(op, (float2*)V, (double2*)H, k, k_done, ws, stream);
+}
+
+// ------------------------------------------------------------------ multishift_fom_restart
+size_t multishift_fom_restart_workspace_bytes(int k, int npoles) {
+  if (k < 1 || k > kMaxK || npoles < 1 || npoles > kMaxPoles) return 0;
+  Carver c;
+  c.take<double>(k + 2);                      // scale (ones)
+  c.take<CycleState>(1);
+  c.take<double2>((size_t)npoles * k);        // Y
+  c.take<double2>((size_t)npoles * k * k);    // U
+  c.take<double2>(k + 1);                     // ucoef
+  c.take<double2>((size_t)npoles * k);        // ycoef
+  c.take<double2>(ts_partial_entries(1, 1));
+  c.take<unsigned>(16);
+  return c.off;
+}
+
+}  // extern "C"
+
+namespace sk {
+__global__ void k_prep_small(double* scale, int k, CycleState* st, const double* beta,
+                             const double2* H, int ld) {
+  int t = threadIdx.x;
+  for (int i = t; i < k + 2; i += blockDim.x) scale[i] = 1.0;
+  if (t == 0) {
+    st->beta = *beta;
+    st->kdone = k;
+    st->breakdown = 0;
+    st->singular = 0;
+    st->nonfinite = 0;
+  }
+}
+
+template <typename T>
+static int msfom_impl(int k, int64_t n, const double2* H, const PoleSet& ps, const double* beta,
+                      double2* rho, const T* V, double2* x, double2* X, double* upd, void* ws,
+                      hipStream_t s) {
+  Carver c;
+  c.base = (char*)ws;
+  double* scale = c.take<double>(k + 2);
+  CycleState* st = c.take<CycleState>(1);
+  double2* Y = c.take<double2>((size_t)ps.n * k);
+  double2* U = c.take<double2>((size_t)ps.n * k * k);
+  double2* ucoef = c.take<double2>(k + 1);
+  double2* ycoef = c.take<double2>((size_t)ps.n * k);
+  double2* partial = c.take<double2>(ts_partial_entries(1, 1));
+  unsigned* counter = c.take<unsigned>(16);
+  ArnoldiDev a;
+  std::memset(&a, 0, sizeof(a));
+  a.H = const_cast<double2*>(H);
+  a.scale = scale;
+  a.st = st;
+  a.ldh = k + 1;
+  a.partial = partial;
+  a.counter = counter;
+  hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(256), 0, s, scale, k, st, beta, H, k + 1);
+  SK_LAUNCH(hipGetLastError());
+  SK_LAUNCH(launch_fom_small(a, k, ps, rho, Y, U, ucoef, X ? ycoef : nullptr, s));
+  TsEpiArgs e = epi_of(EPI_NONE, a);
+  SK_LAUNCH((ts_gemv<T>(V, n, k, ucoef, x, n, true, 0, e, nullptr, nullptr, nullptr, nullptr, s)));
+  if (X) SK_LAUNCH((ts_multi_gemv<T>(V, n, k, ycoef, k, ps.n, X, n, nullptr, s)));
+  CycleState hs;
+  SK_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  SK_HIP(hipStreamSynchronize(s));
+  if (upd) *upd = hs.upd_norm;
+  if (hs.singular) {
+    set_error("H_k - sigma_i is singular for some pole");
+    return SK_ERR_SINGULAR;
+  }
+  if (hs.nonfinite) {
+    set_error("non-finite FOM iterate");
+    return SK_ERR_NAN;
+  }
+  return SK_OK;
+}
+
+}  // namespace sk
+
+extern "C" {
+
+}  // extern "C"
+
+namespace sk {
+static int fill_poles(PoleSet& ps, int npoles, const double* sigma, const double* omega) {
+  SK_CHECK(npoles >= 1 && npoles <= kMaxPoles, "npoles = %d outside [1, %d]", npoles, kMaxPoles);
+  SK_CHECK(sigma && omega, "sigma/omega are NULL");
+  ps.n = npoles;
+  for (int i = 0; i < npoles; ++i) {
+    ps.sigma[i] = make_double2(sigma[2 * i], sigma[2 * i + 1]);
+    ps.omega[i] = make_double2(omega[2 * i], omega[2 * i + 1]);
+    SK_CHECK(std::isfinite(sigma[2 * i]) && std::isfinite(sigma[2 * i + 1]) &&
+                 std::isfinite(omega[2 * i]) && std::isfinite(omega[2 * i + 1]),
+             "pole %d is not finite", i);
+  }
+  return SK_OK;
+}
+
+}  // namespace sk
+
+extern "C" {
+
+int multishift_fom_restart(int k, int64_t n, sk_dtype dtype, const double* H, int npoles,
+                           const double* sigma, const double* omega, const double* beta,
+                           double* rho, const void* V, double* x, double* X_shift,
+                           double* upd_norm, void* ws, size_t ws_bytes, hipStream_t stream) {
+  SK_CHECK(k >= 1 && k <= kMaxK, "k = %d outside [1, %d]", k, kMaxK);
+  SK_CHECK(n >= 1, "n must be positive");
+  SK_CHECK(dtype == SK_C128 || dtype == SK_C64, "unknown dtype");
+  SK_CHECK(H && beta && rho && V && x && ws, "NULL argument");
+  PoleSet ps;
+  SK_TRY(fill_poles(ps, npoles, sigma, omega));
+  const size_t need = multishift_fom_restart_workspace_bytes(k, npoles);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  if (dtype == SK_C128)
+    return msfom_impl<double2>(k, n, (const double2*)H, ps, beta, (double2*)rho, (const double2*)V,
+                               (double2*)x, (double2*)X_shift, upd_norm, ws, stream);
+  return msfom_impl<float2>(k, n, (const double2*)H, ps, beta, (double2*)rho, (const float2*)V,
+                            (double2*)x, (double2*)X_shift, upd_norm, ws, stream);
+}
+
+// ------------------------------------------------------------------ deflate_project
+size_t deflate_project_workspace_bytes(int m, int64_t n) {
+  if (m < 1 || m > kMaxDefl || n < 1) return 0;
+  Carver c;
+  c.take<double2>(ts_partial_entries(n, m));
+  c.take<unsigned>(16);
+  c.take<double2>(m);
+  c.take<CycleState>(1);
+  return c.off;
+}
+
+int deflate_project(int m, int64_t n, const double* R, const double* L, const double* F,
+                    const double* in, double* r_out, double* xp_out, double* coeff, void* ws,
+                    size_t ws_bytes, hipStream_t s) {
+  SK_CHECK(m >= 1 && m <= kMaxDefl, "m = %d outside [1, %d]", m, kMaxDefl);
+  SK_CHECK(n >= 1, "n must be positive");
+  SK_CHECK(R && L && in && r_out && coeff && ws, "NULL argument");
+  SK_CHECK(r_out == in || !overlap(in, n * 16, r_out, n * 16), "r_out partially overlaps in");
+  if (xp_out) {
+    SK_CHECK(F != nullptr, "xp_out requested without F");
+    SK_CHECK(!overlap(xp_out, n * 16, in, n * 16) && !overlap(xp_out, n * 16, r_out, n * 16),
+             "xp_out overlaps in/r_out");
+  }
+  const size_t need = deflate_project_workspace_bytes(m, n);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  Carver c;
+  c.base = (char*)ws;
+  double2* partial = c.take<double2>(ts_partial_entries(n, m));
+  unsigned* counter = c.take<unsigned>(16);
+  double2* fc = c.take<double2>(m);
+  CycleState* st = c.take<CycleState>(1);
+  ArnoldiDev a;
+  std::memset(&a, 0, sizeof(a));
+  a.st = st;
+  SK_LAUNCH(launch_init_state(st, nullptr, 0, counter, 16, s));
+  TsEpiArgs e = epi_of(EPI_DEFL, a);
+  e.out = (double2*)coeff;
+  e.out2 = xp_out ? fc : nullptr;
+  e.F = xp_out ? (const double2*)F : nullptr;
+  SK_LAUNCH((ts_dot<double2, double2>((const double2*)L, n, m, (const double2*)in, n, false, e,
+                                      partial, counter, nullptr, s)));
+  if (xp_out) {
+    TsEpiArgs e0 = epi_of(EPI_NONE, a);
+    SK_LAUNCH((ts_gemv<double2>((const double2*)R, n, m, fc, (double2*)xp_out, n, false, 0, e0,
+                                nullptr, nullptr, nullptr, nullptr, s)));
+  }
+  TsEpiArgs e1 = epi_of(EPI_NONE, a);
+  SK_LAUNCH((ts_update<double2, double2, double2>((const double2*)R, n, m, (const double2*)coeff,
+                                                  nullptr, (const double2*)in, (double2*)r_out, n, 0,
+                                                  e1, partial, counter + 1, nullptr, s)));
+  return SK_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ sign_apply
+namespace sk {
+namespace {
+
+struct SignWs {
+  size_t bytes;
+};
+
+bool params_ok(const sk_sign_params* p, int64_t n, char* msg, size_t len) {
+  if (!p) return snprintf(msg, len, "params are NULL"), false;
+  if (p->npoles < 1 || p->npoles > kMaxPoles) return snprintf(msg, len, "npoles = %d outside [1, %d]", p->npoles, kMaxPoles), false;
+  if (!p->sigma || !p->omega) return snprintf(msg, len, "sigma/omega are NULL"), false;
+  if (p->k < 1 || p->k > kMaxK) return snprintf(msg, len, "k = %d outside [1, %d]", p->k, kMaxK), false;
+  if (p->max_cycles < 1) return snprintf(msg, len, "max_cycles must be >= 1"), false;
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return snprintf(msg, len, "tol must be positive"), false;
+  if (p->m < 0 || p->m > kMaxDefl) return snprintf(msg, len, "m = %d outside [0, %d]", p->m, kMaxDefl), false;
+  if (p->m > 0 && (!p->R || !p->L || !p->F)) return snprintf(msg, len, "m > 0 needs R, L and F"), false;
+  if (p->precision != SK_PREC_FP64 && p->precision != SK_PREC_MIXED) return snprintf(msg, len, "unknown precision %d", p->precision), false;
+  (void)n;
+  return true;
+}
+
+template <typename T>
+size_t sign_ws_bytes(int64_t n, const sk_sign_params* p) {
+  Carver c;
+  KrylovWs<T> w;
+  return carve_krylov(c, w, n, p->k, p->npoles, p->m, p->X_shift != nullptr);
+}
+
+template <typename T>
+int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, double2* x,
+              sk_stats* stats, void* ws, hipStream_t s) {
+  const int64_t n = 12 * volume_of(op);
+  const int k = p->k, m = p->m, N = p->npoles;
+  double2* X = (double2*)p->X_shift;
+  const double2* R = (const double2*)p->R;
+  const double2* Lv = (const double2*)p->L;
+  Carver c;
+  c.base = (char*)ws;
+  KrylovWs<T> w;
+  carve_krylov(c, w, n, k, N, m, X != nullptr);
+  PoleSet ps;
+  SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
+  const ArnoldiDev a = arn_of(w, k);
+
+  SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, 16, s));
+  SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(k + 1) * k * 2, s));
+  if (X) SK_LAUNCH(launch_fill_zero((double*)X, (int64_t)N * n * 2, s));
+  TsEpiArgs eb = epi_of(EPI_BETA, a);
+  eb.dst_scalar = &w.st->beta;
+  eb.dst_scale = w.scale;
+  const TsEpiArgs e0 = epi_of(EPI_NONE, a);
+  // x = x_P = R f(Lambda) L^H b ;  r = (I - P) b  (Algorithm 1, first two lines)
+  if (m > 0) {
+    TsEpiArgs ed = epi_of(EPI_DEFL, a);
+    ed.out = w.dc;
+    ed.out2 = w.dc2;
+    ed.F = (const double2*)p->F;
+    ed.dst_scalar = &w.st->leak;
+    SK_LAUNCH((ts_dot<double2, double2>(Lv, n, m, b, n, false, ed, w.partial, w.counter + 4,
+                                        nullptr, s)));
+    SK_LAUNCH((ts_gemv<double2>(R, n, m, w.dc2, x, n, false, 0, e0, nullptr, nullptr, nullptr,
+                                nullptr, s)));
+    SK_LAUNCH((ts_update<double2, double2, T>(R, n, m, w.dc, nullptr, b, w.W, n, 2, eb, w.partial,
+                                              w.counter + 5, nullptr, s)));
+  } else {
+    SK_LAUNCH(launch_fill_zero((double*)x, n * 2, s));
+    SK_LAUNCH((ts_update<double2, double2, T>((const double2*)nullptr, n, 0, nullptr, nullptr, b,
+                                              w.W, n, 2, eb, w.partial, w.counter + 5, nullptr, s)));
+  }
+  CycleState hs;
+  SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  SK_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->cycles = 0;
+    stats->matvecs = 0;
+    stats->converged = 0;
+    stats->breakdown = 0;
+    stats->final_update_norm = 0.0;
+    stats->x_norm = 0.0;
+  }
+  if (hs.nonfinite || !std::isfinite(hs.beta)) {
+    set_error("source contains non-finite values");
+    return SK_ERR_NAN;
+  }
+  if (hs.beta == 0.0) {   // (I - P) b = 0: x = x_P exactly
+    if (stats) stats->converged = 1;
+    return SK_OK;
+  }
+  const int* skip = &w.st->breakdown;
+  T* Wk = w.W + (size_t)k * n;
+  int small = 0, status = SK_ERR_NOCONV;
+  double beta_cycle = hs.beta, first_upd = 0.0;
+  bool diverged = false;
+  KTimer tm;
+  if (stats && stats->times) {
+    tm.out = stats->times;
+    tm.s = s;
+  }
+  const double cb = (double)sizeof(T), nn = (double)n;
+  for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
+    SK_TRY(enqueue_arnoldi<T>(op, w, n, k, 0, s, &tm));
+    tm.begin(SK_K_SMALL, 0.0);
+    SK_LAUNCH(launch_fom_small(a, k, ps, w.rho, w.Y, w.U, w.ucoef, X ? w.ycoef : nullptr, s));
+    tm.end();
+    TsEpiArgs ex = epi_of(EPI_XNORM, a);
+    ex.dst_scalar = &w.st->xnorm2;
+    tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * nn * 16.0);
+    SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, x, n, true, 2, ex, w.partial, w.counter + 6,
+                          &w.st->kdone, nullptr, s)));
+    tm.end();
+    if (X) {
+      tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * N * nn * 16.0);
+      SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, X, n, &w.st->kdone, s)));
+      tm.end();
+    }
+    // r = v_{k+1};  r = (I - P) r  (projection step)
+    if (m > 0) {
+      TsEpiArgs ed = epi_of(EPI_DEFL, a);
+      ed.out = w.dc;
+      ed.alpha = w.scale + k;
+      ed.dst_scalar = &w.st->leak;
+      tm.begin(SK_K_PROJECT, m * nn * 16.0 + nn * cb);
+      SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7, skip, s)));
+      tm.end();
+    }
+    if (m > 0 && p->project_each_cycle) {
+      tm.begin(SK_K_PROJECT, m * nn * 16.0 + 2.0 * nn * cb);
+      SK_LAUNCH((ts_update<double2, T, T>(R, n, m, w.dc, w.scale + k, Wk, w.W, n, 2, eb, w.partial,
+                                          w.counter + 8, skip, s)));
+      tm.end();
+    } else {
+      tm.begin(SK_K_PROJECT, 2.0 * nn * cb);
+      SK_LAUNCH((ts_update<T, T, T>((const T*)nullptr, n, 0, nullptr, w.scale + k, Wk, w.W, n, 2, eb,
+                                    w.partial, w.counter + 8, skip, s)));
+      tm.end();
+    }
+    SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipStreamSynchronize(s));
+    tm.flush();
+    if (stats) {
+      stats->cycles = cyc + 1;
+      stats->matvecs += hs.kdone;
+      stats->final_update_norm = hs.upd_norm;
+      stats->x_norm = std::sqrt(hs.xnorm2);
+      if (cyc < stats->hist_cap) {
+        if (stats->hist_update) stats->hist_update[cyc] = hs.upd_norm;
+        if (stats->hist_beta) stats->hist_beta[cyc] = beta_cycle;
+        if (stats->hist_leak) stats->hist_leak[cyc] = hs.leak;
+      }
+    }
+    beta_cycle = hs.beta;
+    if (hs.nonfinite) {
+      set_error("non-finite value in cycle %d (restarted FOM diverged or bad input)", cyc + 1);
+      status = SK_ERR_NAN;
+      break;
+    }
+    if (hs.singular) {
+      set_error("H_k - sigma_i singular in cycle %d", cyc + 1);
+      status = SK_ERR_SINGULAR;
+      break;
+    }
+    if (hs.breakdown) {
+      if (stats) stats->breakdown = 1;
+      status = SK_OK;
+      break;
+    }
+    small = (hs.upd_norm <= p->tol * std::sqrt(hs.xnorm2)) ? small + 1 : 0;
+    if (small >= 2) {
+      status = SK_OK;
+      break;
+    }
+    // restarted FOM is not monotone; an update 1e10 times the first one
+    // means the restarted iteration diverges for this k
+    if (cyc == 0) first_upd = hs.upd_norm;
+    else if (hs.upd_norm > kDivergeFactor * first_upd) {
+      set_error("restarted FOM diverged (cycle %d, update %.3e): try another restart length",
+                cyc + 1, hs.upd_norm);
+      status = SK_ERR_NOCONV;
+      diverged = true;
+      break;
+    }
+  }
+  if (stats) stats->converged = (status == SK_OK);
+  if (status == SK_ERR_NOCONV && !diverged) set_error("not converged after %d cycles", p->max_cycles);
+  return status;
+}
+
+}  // namespace
+}  // namespace sk
+
+extern "C" {
+
+size_t sign_apply_workspace_bytes(const sk_operator* op, const sk_sign_params* p) {
+  if (!op || !p || volume_of(op) <= 0) return 0;
+  char msg[256];
+  const int64_t n = 12 * volume_of(op);
+  if (!params_ok(p, n, msg, sizeof msg)) return 0;
+  if (p->precision == SK_PREC_MIXED) return sign_ws_bytes<float2>(n, p);
+  return sign_ws_bytes<double2>(n, p);
+}
+
+int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, double* x,
+               sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
+  const sk_dtype dt = (p && p->precision == SK_PREC_MIXED) ? SK_C64 : SK_C128;
+  SK_TRY(check_operator(op, SK_C128));
+  if (dt == SK_C64) SK_TRY(check_operator(op, SK_C64));
+  const int64_t n = 12 * volume_of(op);
+  char msg[256];
+  SK_CHECK(params_ok(p, n, msg, sizeof msg), "%s", msg);
+  SK_CHECK(b && x && ws, "b, x and ws must be non-NULL");
+  SK_CHECK(!overlap(b, n * 16, x, n * 16), "b and x overlap");
+  if (p->X_shift)
+    SK_CHECK(!overlap(p->X_shift, (size_t)p->npoles * n * 16, x, n * 16) &&
+                 !overlap(p->X_shift, (size_t)p->npoles * n * 16, b, n * 16),
+             "X_shift overlaps b or x");
+  const size_t need = sign_apply_workspace_bytes(op, p);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  SK_CHECK(!overlap(ws, need, x, n * 16) && !overlap(ws, need, b, n * 16), "workspace overlaps b or x");
+  if (p->precision == SK_PREC_MIXED) {
+    set_error("mixed precision is not available in this build");
+    return SK_ERR_ARG;
+  }
+  return sign_impl<double2>(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal helpers shared by the libsignkrylov translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <cstdarg>
+#include <cmath>
+
+#include "signkrylov.h"
+
+namespace sk {
+
+// ----------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+
+#define SK_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      ::sk::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                      __FILE__, __LINE__);                                  \
+      return SK_ERR_HIP;                                                    \
+    }                                                                       \
+  } while (0)
+
+#define SK_CHECK(cond, ...)          \
+  do {                               \
+    if (!(cond)) {                   \
+      ::sk::set_error(__VA_ARGS__);  \
+      return SK_ERR_ARG;             \
+    }                                \
+  } while (0)
+
+#define SK_TRY(call)             \
+  do {                           \
+    int s_ = (call);             \
+    if (s_ != SK_OK) return s_;  \
+  } while (0)
+
+// ----------------------------------------------------------------- complex
+template <typename R> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+
+__host__ __device__ inline double2 mk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cconjmul(double2 a, double2 b) {  // conj(a) * b
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cscale(double2 a, double s) { return mk(a.x * s, a.y * s); }
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm for a / b
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return mk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  } else {
+    double r = b.x / b.y, d = b.y + b.x * r;
+    return mk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+  }
+}
+
+// loads / stores converting between storage precision and double
+__device__ inline double2 ld(const double2* p) { return *p; }
+__device__ inline double2 ld(const float2* p) {
+  float2 v = *p;
+  return mk((double)v.x, (double)v.y);
+}
+__device__ inline void st(double2* p, double2 v) { *p = v; }
+__device__ inline void st(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+// ----------------------------------------------------------------- reductions
+// Wave64 sum of a double (all lanes receive the result).
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+inline int64_t volume_of(const sk_operator* op) {
+  if (!op) return 0;
+  int64_t v = 1;
+  for (int i = 0; i < 4; ++i) {
+    if (op->dims[i] < 1) return 0;
+    v *= op->dims[i];
+  }
+  return v;
+}
+
+int check_operator(const sk_operator* op, sk_dtype dtype);
+
+inline size_t cbytes(sk_dtype d) { return d == SK_C128 ? 16 : 8; }
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace sk

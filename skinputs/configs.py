@@ -1,0 +1,71 @@
+"""The synthetic workloads: lattice sizes, roughness, mu, poles, restarts.
+
+Pure parameters (no arithmetic of the method).  The pole scale c of
+g_s(c x) follows the two-circle rule of Sect. 6, c = ((m+r)(m-r))^{-1/2},
+with m - r = a the smallest |lambda| left after deflation and m + r = b the
+largest |lambda|; a and b were measured once on each configuration's gauge
+field with the CPU oracle (tests/golden/make_golden.py prints them) and c
+is kept to 4 significant digits so both sides use bit-identical poles.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+__all__ = ["Config", "CONFIGS", "pole_scale"]
+
+
+@dataclass(frozen=True)
+class Config:
+    name: str
+    dims: tuple
+    eps: float                 # link roughness U = exp(i eps Q)
+    mus: tuple                 # chemical potentials the config is run at
+    s: int                     # Kenney-Laub order; N = 2 s first-order poles
+    k: int                     # restart length
+    m: int                     # deflation dimension
+    tol: float                 # stopping tolerance on the update norm
+    precision: str = "fp64"    # "fp64" or "mixed"
+    kappa: float = 0.25        # m_W = -2
+    antiperiodic_t: bool = True
+    max_cycles: int = 400
+    scales: dict = field(default_factory=dict)   # mu -> c
+
+    @property
+    def L(self):
+        return self.dims[0]
+
+    @property
+    def V(self):
+        d = self.dims
+        return d[0] * d[1] * d[2] * d[3]
+
+    @property
+    def n(self):
+        return 12 * self.V
+
+    @property
+    def npoles(self):
+        return 2 * self.s
+
+
+CONFIGS = {
+    # 4^4, 10 poles, k = 20, no deflation, complex double
+    "c1": Config("c1", (4, 4, 4, 4), 0.5, (0.3,), s=5, k=20, m=0, tol=1e-10,
+                 scales={0.3: 1.390}),
+    # 8^4, 16 poles, k = 50, 20 deflated (oblique, left + right), complex double
+    "c2": Config("c2", (8, 8, 8, 8), 0.6, (0.1, 0.3), s=8, k=50, m=20, tol=1e-10,
+                 scales={0.1: 1.864, 0.3: 1.827}),
+    # 10^4, 16 poles, k = 60, 40 deflated, complex-float stencil/basis + FP64
+    "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-10,
+                 precision="mixed", scales={}),
+    # backward: 8^4, mu = 0.3, 16 poles, k = 50, no deflation
+    "cg": Config("cg", (8, 8, 8, 8), 0.6, (0.3,), s=8, k=50, m=0, tol=1e-10,
+                 scales={0.3: 1.917}),
+}
+
+
+def pole_scale(cfg: Config, mu: float) -> float:
+    try:
+        return cfg.scales[mu]
+    except KeyError:
+        raise KeyError(f"no pole scale recorded for config {cfg.name} at mu={mu}") from None

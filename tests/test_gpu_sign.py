@@ -1,0 +1,165 @@
+"""GPU parity of sign_apply (Algorithm 1, restarted FOM-LR) against the
+oracle's x* = R sign(Lambda) L^H b + sum_j omega_j (H - sigma_j)^{-1}(I - R L^H) b,
+on lattices small enough for dense algebra."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import skinputs as si
+from skinputs.configs import CONFIGS
+from oracle import dirac, rational, xstar, deflation
+from tests.gpu_util import make_op, to_dev, from_dev, vecs_to_dev, rel, announce, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-8   # relative 2-norm error bound of the FP64 path
+
+
+def _problem(dims, eps, mu, seed_g, seed_b):
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, eps, seed_g)
+    b = si.gaussian_source(12 * V, seed_b)
+    A = dirac.hw_dense(U, dims, 0.25, mu)
+    return V, U, b, A
+
+
+def test_config_c1_matches_oracle():
+    from paper_0910_2927_amd import api
+    cfg = CONFIGS["c1"]
+    mu = cfg.mus[0]
+    V, U, b, A = _problem(cfg.dims, cfg.eps, mu, si.seed_for(cfg.L, "gauge"), si.seed_for(cfg.L, "b"))
+    sig, om = rational.kl_first_order(cfg.s, cfg.scales[mu])
+    announce("sign_apply c1 4^4 k=20 N=10")
+    op = make_op(U, cfg.dims, cfg.kappa, mu)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles)
+    assert res.converged
+    ref = xstar.xstar_dense(A, b, sig, om)
+    err = rel(from_dev(res.x, V), ref)
+    print(f"c1: cycles={res.cycles} matvecs={res.matvecs} err={err:.2e}")
+    assert err <= TOL_FP64
+
+
+@pytest.mark.parametrize("k", [12, 37])
+def test_ragged_lattice_with_deflation(k):
+    from paper_0910_2927_amd import api
+    import torch
+    dims = (3, 4, 5, 6)
+    V, U, b, A = _problem(dims, 0.6, 0.3, 91, 92)
+    R, L, lam, F = deflation.lr_dense(A, 24)
+    sig, om = rational.kl_first_order(8, 1.5)
+    announce(f"sign_apply ragged 3x4x5x6 m=24 k={k}")
+    op = make_op(U, dims, 0.25, 0.3)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, k, tol=1e-11, max_cycles=400,
+                         R=vecs_to_dev(R, V), Lv=vecs_to_dev(L, V),
+                         F=torch.from_numpy(F).to(torch_dev()))
+    assert res.converged
+    ref = xstar.xstar_dense(A, b, sig, om, R, L, F)
+    err = rel(from_dev(res.x, V), ref)
+    print(f"ragged k={k}: cycles={res.cycles} err={err:.2e} leak={res.leaks[-1]:.1e}")
+    assert err <= TOL_FP64
+
+
+def test_per_shift_solutions_match_dense_solves():
+    from paper_0910_2927_amd import api
+    dims = (2, 3, 4, 5)
+    V, U, b, A = _problem(dims, 0.5, 0.3, 93, 94)
+    sig, om = rational.kl_first_order(5, 1.2)
+    announce("sign_apply keep_shift_solutions 2x3x4x5")
+    op = make_op(U, dims, 0.25, 0.3)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, 16, tol=1e-12, max_cycles=400,
+                         keep_shift_solutions=True)
+    assert res.converged
+    ref, Xref = xstar.xstar_dense(A, b, sig, om, return_shifts=True)
+    for i in range(len(sig)):
+        assert rel(from_dev(res.X_shift[i], V), Xref[i]) <= 1e-9
+    # the combination sum omega_i X_i is the returned x
+    comb = sum(om[i] * from_dev(res.X_shift[i], V) for i in range(len(sig)))
+    assert rel(comb, from_dev(res.x, V)) < 1e-12
+
+
+def test_plane_wave_source_ends_in_one_cycle_with_closed_form():
+    from paper_0910_2927_amd import api
+    dims = (4, 4, 4, 4)
+    V = 256
+    s = np.arange(V)
+    x, z, t = s % 4, (s // 16) % 4, s // 64
+    ph = np.exp(1j * (np.pi / 2 * x + np.pi * z + (np.pi / 4 + np.pi / 2) * t))
+    b = (ph[:, None, None] * si.gaussian_source(12, 15).reshape(4, 3)[None]).reshape(-1)
+    sig, om = rational.kl_first_order(5, 0.7)
+    announce("sign_apply plane-wave breakdown")
+    op = make_op(si.unit_links(dims), dims, 0.25, 0.3)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, 10, tol=1e-10)
+    assert res.converged and res.breakdown and res.cycles == 1 and res.matvecs == 2
+    ref = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: rational.kl_closed_form(0.7 * l, 5))
+    assert rel(from_dev(res.x, V), ref) < 1e-12
+
+
+def test_restart_length_independence_and_divergence():
+    """Converged results do not depend on k.  Restarted FOM is not monotone:
+    on this problem k = 25 diverges -- in the CPU oracle too -- and the
+    library must say so instead of returning garbage."""
+    from paper_0910_2927_amd import api, _lib
+    from oracle import krylov
+    dims = (4, 4, 4, 4)
+    V, U, b, A = _problem(dims, 0.5, 0.3, 95, 96)
+    sig, om = rational.kl_first_order(6, 1.4)
+    op = make_op(U, dims, 0.25, 0.3)
+    ref = xstar.xstar_dense(A, b, sig, om)
+    for k in (10, 60):
+        announce(f"sign_apply restart length k={k}")
+        res = api.sign_apply(op, to_dev(b, V), sig, om, k, tol=1e-11, max_cycles=1000)
+        assert res.converged
+        assert rel(from_dev(res.x, V), ref) <= TOL_FP64
+    _, info = krylov.restarted_fom_lr(lambda v: A @ v, b, sig, om, k=25, tol_update=1e-11,
+                                      max_cycles=1000)
+    assert not info["converged"]
+    announce("sign_apply restart length k=25 (diverges)")
+    res = api.sign_apply(op, to_dev(b, V), sig, om, 25, tol=1e-11, max_cycles=1000,
+                         raise_on_error=False)
+    assert res.status == _lib.SK_ERR_NOCONV and not res.converged
+    assert res.cycles == len(info["update_norms"])   # same cycle at which both give up
+
+
+def test_error_paths_forced_from_the_host():
+    from paper_0910_2927_amd import api, _lib
+    dims = (2, 2, 2, 4)
+    V, U, b, A = _problem(dims, 0.5, 0.3, 97, 98)
+    sig, om = rational.kl_first_order(5, 1.2)
+    op = make_op(U, dims, 0.25, 0.3)
+    announce("sign_apply error paths")
+    # non-convergence: one cycle only, x holds the iterate
+    res = api.sign_apply(op, to_dev(b, V), sig, om, 4, tol=1e-14, max_cycles=1, raise_on_error=False)
+    assert res.status == _lib.SK_ERR_NOCONV and res.cycles == 1 and not res.converged
+    assert np.all(np.isfinite(from_dev(res.x, V)))
+    # NaN in the source
+    bn = b.copy()
+    bn[5] = np.nan
+    res = api.sign_apply(op, to_dev(bn, V), sig, om, 8, tol=1e-10, raise_on_error=False)
+    assert res.status == _lib.SK_ERR_NAN
+    # bad restart length is rejected before any launch
+    with pytest.raises(_lib.SkError) as e:
+        api.sign_apply(op, to_dev(b, V), sig, om, 0, tol=1e-10)
+    assert e.value.status == _lib.SK_ERR_ARG
+    # undersized workspace: refused on the host, nothing launched
+    solver = api.SignSolver(op, sig, om, 8, tol=1e-10)
+    lib = _lib.load()
+    bd = to_dev(b, V)
+    xd = bd.clone()
+    st = lib.sign_apply(C.byref(solver.opstruct), C.byref(solver.params), C.c_void_p(bd.data_ptr()),
+                        C.c_void_p(xd.data_ptr()), None, C.c_void_p(solver.ws.data_ptr()), 16, None)
+    assert st == _lib.SK_ERR_WORKSPACE
+
+
+def test_zero_source_and_deterministic_repeat():
+    from paper_0910_2927_amd import api
+    dims = (2, 2, 3, 4)
+    V, U, b, A = _problem(dims, 0.5, 0.3, 99, 100)
+    sig, om = rational.kl_first_order(5, 1.2)
+    op = make_op(U, dims, 0.25, 0.3)
+    announce("sign_apply zero source / repeat")
+    res = api.sign_apply(op, to_dev(np.zeros_like(b), V), sig, om, 8, tol=1e-10)
+    assert res.converged and float(res.x.abs().max()) == 0.0
+    r1 = api.sign_apply(op, to_dev(b, V), sig, om, 8, tol=1e-10)
+    r2 = api.sign_apply(op, to_dev(b, V), sig, om, 8, tol=1e-10)
+    assert bool((r1.x == r2.x).all())   # fixed reduction order: bitwise repeatable
