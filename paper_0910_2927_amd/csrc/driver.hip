@@ -67,6 +67,8 @@ struct KrylovWs {
   double2* ycoef;
   double2* dc;
   double2* dc2;
+  double2* gpart;      // CGS2 partial dots, gs_row_blocks(n) x (k+2)
+  double* norm_part;   // partial ||w||^2, gs_row_blocks(n)
 };
 
 template <typename T>
@@ -78,7 +80,7 @@ size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int
   w.wnorm = c.template take<double>(k + 1);
   w.coef = c.template take<double2>(kMaxK + 4);
   w.partial = c.template take<double2>(ts_partial_entries(n, pmax));
-  w.counter = c.template take<unsigned>(16);
+  w.counter = c.template take<unsigned>((size_t)kCounterSlots * ts_counter_stride(n));
   w.st = c.template take<CycleState>(1);
   w.rho = c.template take<double2>(npoles > 0 ? npoles : 1);
   w.Y = c.template take<double2>((size_t)(npoles > 0 ? npoles : 1) * k);
@@ -87,6 +89,8 @@ size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int
   w.ycoef = keep ? c.template take<double2>((size_t)npoles * k) : nullptr;
   w.dc = c.template take<double2>(m > 0 ? m : 1);
   w.dc2 = c.template take<double2>(m > 0 ? m : 1);
+  w.gpart = c.template take<double2>((size_t)gs_row_blocks(n) * (k + 2));
+  w.norm_part = c.template take<double>(gs_row_blocks(n));
   return c.off;
 }
 
@@ -189,25 +193,35 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
   KTimer dummy;
   KTimer& t = tm ? *tm : dummy;
   const double c = (double)sizeof(T), nn = (double)n;
+  const int nrb = gs_row_blocks(n);
   for (int j = 0; j < k; ++j) {
     T* wj1 = w.W + (size_t)(j + 1) * n;
+    ScaleSrc src;
+    std::memset(&src, 0, sizeof(src));
+    src.arn = a;
+    src.nrb = nrb;
+    if (j == 0) {
+      src.in_scale = w.scale;
+    } else {
+      src.norm_part = w.norm_part;
+      src.jprev = j - 1;
+    }
     // stencil: 12 in + 36 link + 12 out complex per site = 5 n complex
     t.begin(SK_K_STENCIL, 5.0 * nn * c);
-    SK_LAUNCH((launch_wilson<T, T, T>(op, U, w.W + (size_t)j * n, wj1, adjoint, w.scale + j, skip, s)));
+    SK_LAUNCH((launch_wilson_arnoldi<T, T, T>(op, U, w.W + (size_t)j * n, wj1, adjoint, src, skip, s)));
     t.end();
     t.begin(SK_K_GS_DOT, (j + 2) * nn * c);
-    SK_LAUNCH((ts_dot<T, T>(w.W, n, j + 1, wj1, n, true, epi_of(EPI_ARN_H1, a, j), w.partial,
-                            w.counter + 0, skip, s)));
+    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, true, w.gpart, skip, s)));
     t.end();
-    t.begin(SK_K_GS_UPD_DOT, (j + 3) * nn * c);
-    SK_LAUNCH((ts_update<T, T, T>(w.W, n, j + 1, w.coef, nullptr, wj1, wj1, n, 1,
-                                  epi_of(EPI_ARN_H2, a, j), w.partial, w.counter + 1, skip, s)));
+    t.begin(SK_K_GS_UPD_DOT, (2 * j + 4) * nn * c);
+    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 1, w.gpart, a, w.norm_part, skip, s)));
+    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, false, w.gpart, skip, s)));
     t.end();
     t.begin(SK_K_GS_UPD_NORM, (j + 3) * nn * c);
-    SK_LAUNCH((ts_update<T, T, T>(w.W, n, j + 1, w.coef, nullptr, wj1, wj1, n, 2,
-                                  epi_of(EPI_ARN_NORM, a, j), w.partial, w.counter + 2, skip, s)));
+    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 2, w.gpart, a, w.norm_part, skip, s)));
     t.end();
   }
+  SK_LAUNCH(gs_finish(w.norm_part, n, k - 1, a, skip, s));
   return SK_OK;
 }
 
@@ -272,9 +286,11 @@ static size_t carve_arnoldi(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
   w.wnorm = c.template take<double>(k + 1);
   w.coef = c.template take<double2>(kMaxK + 4);
   w.partial = c.template take<double2>(ts_partial_entries(n, k));
-  w.counter = c.template take<unsigned>(16);
+  w.counter = c.template take<unsigned>((size_t)kCounterSlots * ts_counter_stride(n));
   w.st = c.template take<CycleState>(1);
   w.rho = c.template take<double2>(1);
+  w.gpart = c.template take<double2>((size_t)gs_row_blocks(n) * (k + 2));
+  w.norm_part = c.template take<double>(gs_row_blocks(n));
   return c.off;
 }
 
@@ -303,13 +319,14 @@ static int arnoldi_impl(const sk_operator* op, T* V, double2* H, int k, int* k_d
   w.W = V;
   w.H = H;
   const ArnoldiDev a = arn_of(w, k);
-  SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, 16, s));
+  const int cs = ts_counter_stride(n);
+  SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, kCounterSlots * cs, s));
   SK_LAUNCH(launch_fill_zero((double*)H, (int64_t)(k + 1) * k * 2, s));
   // normalise the start vector: scale[0] = 1/||V_0||
   TsEpiArgs eb = epi_of(EPI_BETA, a);
   eb.dst_scalar = &w.st->beta;
   eb.dst_scale = w.scale;
-  SK_LAUNCH((ts_dot<T, T>(V, n, 0, V, n, true, eb, w.partial, w.counter + 3, nullptr, s)));
+  SK_LAUNCH((ts_dot<T, T>(V, n, 0, V, n, true, eb, w.partial, w.counter + 3 * cs, nullptr, s)));
   SK_TRY(enqueue_arnoldi<T>(op, w, n, k, 0, s));
   SK_LAUNCH((ts_scale_basis<T>(V, n, k + 1, w.scale, &w.st->kdone, n, s)));
   CycleState hs;
@@ -359,7 +376,7 @@ size_t multishift_fom_restart_workspace_bytes(int k, int npoles) {
   c.take<double2>(k + 1);                     // ucoef
   c.take<double2>((size_t)npoles * k);        // ycoef
   c.take<double2>(ts_partial_entries(1, 1));
-  c.take<unsigned>(16);
+  c.take<unsigned>(kCounterSlots * ts_counter_stride(1));
   return c.off;
 }
 
@@ -392,7 +409,7 @@ static int msfom_impl(int k, int64_t n, const double2* H, const PoleSet& ps, con
   double2* ucoef = c.take<double2>(k + 1);
   double2* ycoef = c.take<double2>((size_t)ps.n * k);
   double2* partial = c.take<double2>(ts_partial_entries(1, 1));
-  unsigned* counter = c.take<unsigned>(16);
+  unsigned* counter = c.take<unsigned>(kCounterSlots * ts_counter_stride(1));
   ArnoldiDev a;
   std::memset(&a, 0, sizeof(a));
   a.H = const_cast<double2*>(H);
@@ -474,7 +491,7 @@ size_t deflate_project_workspace_bytes(int m, int64_t n) {
   if (m < 1 || m > kMaxDefl || n < 1) return 0;
   Carver c;
   c.take<double2>(ts_partial_entries(n, m));
-  c.take<unsigned>(16);
+  c.take<unsigned>(2 * ts_counter_stride(n));
   c.take<double2>(m);
   c.take<CycleState>(1);
   return c.off;
@@ -500,13 +517,14 @@ int deflate_project(int m, int64_t n, const double* R, const double* L, const do
   Carver c;
   c.base = (char*)ws;
   double2* partial = c.take<double2>(ts_partial_entries(n, m));
-  unsigned* counter = c.take<unsigned>(16);
+  const int cs = ts_counter_stride(n);
+  unsigned* counter = c.take<unsigned>(2 * cs);
   double2* fc = c.take<double2>(m);
   CycleState* st = c.take<CycleState>(1);
   ArnoldiDev a;
   std::memset(&a, 0, sizeof(a));
   a.st = st;
-  SK_LAUNCH(launch_init_state(st, nullptr, 0, counter, 16, s));
+  SK_LAUNCH(launch_init_state(st, nullptr, 0, counter, 2 * cs, s));
   TsEpiArgs e = epi_of(EPI_DEFL, a);
   e.out = (double2*)coeff;
   e.out2 = xp_out ? fc : nullptr;
@@ -521,7 +539,7 @@ int deflate_project(int m, int64_t n, const double* R, const double* L, const do
   TsEpiArgs e1 = epi_of(EPI_NONE, a);
   SK_LAUNCH((ts_update<double2, double2, double2>((const double2*)R, n, m, (const double2*)coeff,
                                                   nullptr, (const double2*)in, (double2*)r_out, n, 0,
-                                                  e1, partial, counter + 1, nullptr, s)));
+                                                  e1, partial, counter + cs, nullptr, s)));
   return SK_OK;
 }
 
@@ -571,8 +589,9 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   PoleSet ps;
   SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
   const ArnoldiDev a = arn_of(w, k);
+  const int cs = ts_counter_stride(n);
 
-  SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, 16, s));
+  SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, kCounterSlots * cs, s));
   SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(k + 1) * k * 2, s));
   if (X) SK_LAUNCH(launch_fill_zero((double*)X, (int64_t)N * n * 2, s));
   TsEpiArgs eb = epi_of(EPI_BETA, a);
@@ -586,16 +605,16 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     ed.out2 = w.dc2;
     ed.F = (const double2*)p->F;
     ed.dst_scalar = &w.st->leak;
-    SK_LAUNCH((ts_dot<double2, double2>(Lv, n, m, b, n, false, ed, w.partial, w.counter + 4,
+    SK_LAUNCH((ts_dot<double2, double2>(Lv, n, m, b, n, false, ed, w.partial, w.counter + 4 * cs,
                                         nullptr, s)));
     SK_LAUNCH((ts_gemv<double2>(R, n, m, w.dc2, x, n, false, 0, e0, nullptr, nullptr, nullptr,
                                 nullptr, s)));
     SK_LAUNCH((ts_update<double2, double2, T>(R, n, m, w.dc, nullptr, b, w.W, n, 2, eb, w.partial,
-                                              w.counter + 5, nullptr, s)));
+                                              w.counter + 5 * cs, nullptr, s)));
   } else {
     SK_LAUNCH(launch_fill_zero((double*)x, n * 2, s));
     SK_LAUNCH((ts_update<double2, double2, T>((const double2*)nullptr, n, 0, nullptr, nullptr, b,
-                                              w.W, n, 2, eb, w.partial, w.counter + 5, nullptr, s)));
+                                              w.W, n, 2, eb, w.partial, w.counter + 5 * cs, nullptr, s)));
   }
   CycleState hs;
   SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -635,7 +654,7 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     TsEpiArgs ex = epi_of(EPI_XNORM, a);
     ex.dst_scalar = &w.st->xnorm2;
     tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * nn * 16.0);
-    SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, x, n, true, 2, ex, w.partial, w.counter + 6,
+    SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, x, n, true, 2, ex, w.partial, w.counter + 6 * cs,
                           &w.st->kdone, nullptr, s)));
     tm.end();
     if (X) {
@@ -650,18 +669,18 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
       ed.alpha = w.scale + k;
       ed.dst_scalar = &w.st->leak;
       tm.begin(SK_K_PROJECT, m * nn * 16.0 + nn * cb);
-      SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7, skip, s)));
+      SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7 * cs, skip, s)));
       tm.end();
     }
     if (m > 0 && p->project_each_cycle) {
       tm.begin(SK_K_PROJECT, m * nn * 16.0 + 2.0 * nn * cb);
       SK_LAUNCH((ts_update<double2, T, T>(R, n, m, w.dc, w.scale + k, Wk, w.W, n, 2, eb, w.partial,
-                                          w.counter + 8, skip, s)));
+                                          w.counter + 8 * cs, skip, s)));
       tm.end();
     } else {
       tm.begin(SK_K_PROJECT, 2.0 * nn * cb);
       SK_LAUNCH((ts_update<T, T, T>((const T*)nullptr, n, 0, nullptr, w.scale + k, Wk, w.W, n, 2, eb,
-                                    w.partial, w.counter + 8, skip, s)));
+                                    w.partial, w.counter + 8 * cs, skip, s)));
       tm.end();
     }
     SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));

