@@ -219,6 +219,58 @@ size_t sign_apply_workspace_bytes(const sk_operator* op, const sk_sign_params* p
 int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, double* x,
                sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Deflation data for Algorithm 1: the m "critical" eigenvalues of H_W
+ * (Sect. 4 -- the paper takes R_m, L_m, Lambda_m as given inputs).
+ * Krylov-Schur (thick-restart Arnoldi) on A^2 for its eigenvalues of
+ * smallest real part finds the eigenvalues of A nearest zero (their squares
+ * sit at the left edge of the spectrum of A^2); m + nev_extra of them are
+ * computed so the selection can be certified (every |lambda| <= the m-th
+ * selected one must be among them).  The same on A^H = H_W(-mu) gives the
+ * left invariant subspace.  Output, in an orthonormal Schur basis of the
+ * right invariant subspace (an oblique projector equal to the LR one):
+ *   R (device, m x n complex double): orthonormal, A R = R T_m;
+ *   L (device, m x n complex double): L^H R = I, L^H A = T_m L^H;
+ *   F (device, m x m complex double, column-major): sign(T_m) (Newton);
+ *   lambda (host, m complex): diag(T_m), sorted by the selection key.
+ * P = R L^H and x_P = R F L^H b are exactly the R_m f(Lambda_m) L_m^H of
+ * Sect. 4.  The small dense problems (Schur forms, sorting, sign) run in
+ * FP64 on the host inside the library.
+ */
+typedef struct {
+  int32_t m;             /* eigenpairs to deflate, 1..128 */
+  int32_t nev_extra;     /* extra Ritz pairs computed to certify the selection */
+  int32_t ncv;           /* Krylov-Schur basis size (0: automatic) */
+  int32_t key;           /* 0: smallest |lambda|, 1: smallest |Re lambda| */
+  double tol;            /* relative residual of the converged A^2 Schur vectors */
+  int32_t max_restarts;
+} sk_eig_params;
+
+typedef struct {
+  int32_t converged;
+  int32_t restarts[2];   /* right, left */
+  int64_t matvecs;       /* H_W applications */
+  double resid[2];       /* largest relative A^2 Schur residual, right / left */
+  double gap;            /* key gap between the m-th and (m+1)-th eigenvalue */
+  double key_window;     /* largest Re(lambda^2) computed (certification) */
+} sk_eig_stats;
+
+size_t deflation_eigensolve_workspace_bytes(const sk_operator* op, const sk_eig_params* p);
+int deflation_eigensolve(const sk_operator* op, const sk_eig_params* p, double* R, double* L,
+                         double* F, double* lambda, sk_eig_stats* stats, void* ws,
+                         size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Host helpers exposing the library's small dense FP64 routines (used by the
+ * eigensolver), column-major complex (re, im) arrays, host memory:
+ *   sk_dense_schur: A (n x n) = Q T Q^H, T upper triangular, with the
+ *     `count` eigenvalues of smallest key first (key 0: Re, 1: |.|, 2: |Re|).
+ *   sk_dense_sign: S = sign(A) by Newton's iteration (Roberts' method).
+ * Return SK_OK, or SK_ERR_NOCONV / SK_ERR_SINGULAR.
+ */
+int sk_dense_schur(int n, const double* A, double* T, double* Q, int key, int count);
+int sk_dense_sign(int n, const double* A, double* S);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,16 @@ class SkStats(C.Structure):
                 ("hist_cap", C.c_int32), ("times", C.POINTER(SkKernelTimes))]
 
 
+class SkEigParams(C.Structure):
+    _fields_ = [("m", C.c_int32), ("nev_extra", C.c_int32), ("ncv", C.c_int32), ("key", C.c_int32),
+                ("tol", C.c_double), ("max_restarts", C.c_int32)]
+
+
+class SkEigStats(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("restarts", C.c_int32 * 2), ("matvecs", C.c_int64),
+                ("resid", C.c_double * 2), ("gap", C.c_double), ("key_window", C.c_double)]
+
+
 # (name, restype, argtypes) of every exported symbol
 SIGNATURES = [
     ("sk_volume", C.c_int64, [C.POINTER(SkOperator)]),
@@ -85,6 +95,14 @@ SIGNATURES = [
     ("sign_apply_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator), C.POINTER(SkSignParams)]),
     ("sign_apply", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,
                              C.c_void_p, C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("deflation_eigensolve_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator),
+                                                          C.POINTER(SkEigParams)]),
+    ("deflation_eigensolve", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkEigParams), C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                       C.POINTER(SkEigStats), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("sk_dense_schur", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_int, C.c_int]),
+    ("sk_dense_sign", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
 ]
 
 _lib = None

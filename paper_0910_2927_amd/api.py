@@ -154,6 +154,62 @@ def deflate_project(R, Lv, v, F=None):
     return r, coeff, xp
 
 
+def deflation_eigensolve(op: WilsonOperator, m, nev_extra=16, ncv=0, key="abs", tol=1e-11,
+                         max_restarts=2000):
+    """The m eigenpairs of H_W nearest zero as an oblique projector:
+    returns (R (m, n), L (m, n), F (m, m) = sign(T_m), lambda (numpy), stats)."""
+    lib = L.load()
+    p = L.SkEigParams()
+    p.m, p.nev_extra, p.ncv = int(m), int(nev_extra), int(ncv)
+    p.key = 0 if key == "abs" else 1
+    p.tol, p.max_restarts = float(tol), int(max_restarts)
+    s = op.struct()
+    nb = lib.deflation_eigensolve_workspace_bytes(C.byref(s), C.byref(p))
+    if nb == 0:
+        raise SkError(L.SK_ERR_ARG, "invalid eigensolver parameters")
+    ws = _workspace(nb, op.device)
+    R = torch.empty((m, op.n), dtype=torch.complex128, device=op.device)
+    Lv = torch.empty_like(R)
+    Fc = torch.empty((m, m), dtype=torch.complex128, device=op.device)   # column-major
+    lam = (C.c_double * (2 * m))()
+    st = L.SkEigStats()
+    L.check(lib.deflation_eigensolve(C.byref(s), C.byref(p), _ptr(R), _ptr(Lv), _ptr(Fc), lam,
+                                     C.byref(st), _ptr(ws), ws.numel(), _stream()))
+    lamv = np.frombuffer(lam, dtype=np.float64).copy().view(np.complex128)
+    stats = {"restarts": tuple(st.restarts), "matvecs": st.matvecs, "resid": tuple(st.resid),
+             "gap": st.gap, "key_window": st.key_window}
+    return R, Lv, Fc.transpose(0, 1).contiguous(), lamv, stats
+
+
+def _host_cplx(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return a, a.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))
+
+
+def dense_schur(A, key="re", count=None):
+    """Library's host Schur form: A = Q T Q^H with `count` eigenvalues of
+    smallest key first (key: "re", "abs", "absre")."""
+    lib = L.load()
+    n = A.shape[0]
+    Af, pa = _host_cplx(np.asarray(A, dtype=np.complex128).reshape(-1, order="F"))
+    T = np.zeros(n * n, dtype=np.complex128)
+    Q = np.zeros(n * n, dtype=np.complex128)
+    kmap = {"re": 0, "abs": 1, "absre": 2}
+    L.check(lib.sk_dense_schur(n, pa, T.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                               Q.view(np.float64).ctypes.data_as(C.POINTER(C.c_double)),
+                               kmap[key], n if count is None else int(count)))
+    return T.reshape(n, n, order="F"), Q.reshape(n, n, order="F")
+
+
+def dense_sign(A):
+    lib = L.load()
+    n = A.shape[0]
+    Af, pa = _host_cplx(np.asarray(A, dtype=np.complex128).reshape(-1, order="F"))
+    S = np.zeros(n * n, dtype=np.complex128)
+    L.check(lib.sk_dense_sign(n, pa, S.view(np.float64).ctypes.data_as(C.POINTER(C.c_double))))
+    return S.reshape(n, n, order="F")
+
+
 @dataclass
 class SignResult:
     x: torch.Tensor

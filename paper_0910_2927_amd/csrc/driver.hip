@@ -1,7 +1,7 @@
 // Host side of libsignkrylov: argument checks, workspace layout, and the
 // restart loop of Algorithm 1 (restarted FOM-LR(m,k)) built from the
 // kernels in wilson.hip, tsla.hip and small.hip.
-#include "sk_internal.h"
+#include "krylov_ws.h"
 
 #include <cstring>
 #include <mutex>
@@ -31,199 +31,6 @@ int check_operator(const sk_operator* op, sk_dtype dtype) {
 }
 
 namespace {
-
-bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-  const char* pa = (const char*)a;
-  const char* pb = (const char*)b;
-  return pa < pb + nb && pb < pa + na;
-}
-
-// Carves the caller's workspace into aligned pieces.
-struct Carver {
-  size_t off = 0;
-  char* base = nullptr;
-  template <typename T> T* take(size_t count) {
-    size_t o = off;
-    off = align256(off + count * sizeof(T));
-    return base ? reinterpret_cast<T*>(base + o) : nullptr;
-  }
-};
-
-// Device scratch used by an Arnoldi-based driver.
-template <typename T>
-struct KrylovWs {
-  T* W;                // (k+1) basis slots, unnormalised: v_j = scale[j] W_j
-  double2* H;
-  double* scale;
-  double* wnorm;
-  double2* coef;
-  double2* partial;
-  unsigned* counter;
-  CycleState* st;
-  double2* rho;
-  double2* Y;
-  double2* U;
-  double2* ucoef;
-  double2* ycoef;
-  double2* dc;
-  double2* dc2;
-  double2* gpart;      // CGS2 partial dots, gs_row_blocks(n) x (k+2)
-  double* norm_part;   // partial ||w||^2, gs_row_blocks(n)
-};
-
-template <typename T>
-size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int m, bool keep) {
-  const int pmax = k > m ? k : m;
-  w.W = c.template take<T>((size_t)(k + 1) * n);
-  w.H = c.template take<double2>((size_t)(k + 1) * k);
-  w.scale = c.template take<double>(k + 2);
-  w.wnorm = c.template take<double>(k + 1);
-  w.coef = c.template take<double2>(kMaxK + 4);
-  w.partial = c.template take<double2>(ts_partial_entries(n, pmax));
-  w.counter = c.template take<unsigned>((size_t)kCounterSlots * ts_counter_stride(n));
-  w.st = c.template take<CycleState>(1);
-  w.rho = c.template take<double2>(npoles > 0 ? npoles : 1);
-  w.Y = c.template take<double2>((size_t)(npoles > 0 ? npoles : 1) * k);
-  w.U = c.template take<double2>((size_t)(npoles > 0 ? npoles : 1) * k * k);
-  w.ucoef = c.template take<double2>(k + 1);
-  w.ycoef = keep ? c.template take<double2>((size_t)npoles * k) : nullptr;
-  w.dc = c.template take<double2>(m > 0 ? m : 1);
-  w.dc2 = c.template take<double2>(m > 0 ? m : 1);
-  w.gpart = c.template take<double2>((size_t)gs_row_blocks(n) * (k + 2));
-  w.norm_part = c.template take<double>(gs_row_blocks(n));
-  return c.off;
-}
-
-template <typename T>
-ArnoldiDev arn_of(const KrylovWs<T>& w, int k) {
-  ArnoldiDev a;
-  a.H = w.H;
-  a.scale = w.scale;
-  a.wnorm = w.wnorm;
-  a.coef = w.coef;
-  a.partial = w.partial;
-  a.counter = w.counter;
-  a.st = w.st;
-  a.ldh = k + 1;
-  return a;
-}
-
-TsEpiArgs epi_of(int kind, const ArnoldiDev& a, int j = 0) {
-  TsEpiArgs e;
-  std::memset(&e, 0, sizeof(e));
-  e.epi = kind;
-  e.j = j;
-  e.arn = a;
-  return e;
-}
-
-// Optional per-kernel timing: HIP events around every launch of a solve,
-// summed per kernel class after each cycle's host synchronisation.
-struct KTimer {
-  sk_kernel_times* out = nullptr;
-  hipStream_t s = nullptr;
-  std::vector<hipEvent_t> pool;
-  struct Rec { int cls; double bytes; int e0, e1; };
-  std::vector<Rec> recs;
-  size_t used = 0;
-  int cur_cls = 0, cur_e0 = 0;
-  double cur_bytes = 0.0;
-  bool on() const { return out != nullptr; }
-  int record() {
-    if (used == pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return -1;
-      pool.push_back(e);
-    }
-    hipEventRecord(pool[used], s);
-    return (int)used++;
-  }
-  void begin(int cls, double bytes) {
-    if (!on()) return;
-    cur_cls = cls;
-    cur_bytes = bytes;
-    cur_e0 = record();
-  }
-  void end() {
-    if (!on()) return;
-    int e1 = record();
-    if (cur_e0 >= 0 && e1 >= 0) recs.push_back({cur_cls, cur_bytes, cur_e0, e1});
-  }
-  // call after the stream has been synchronised
-  void flush() {
-    if (!on()) return;
-    for (const Rec& r : recs) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, pool[r.e0], pool[r.e1]) == hipSuccess) {
-        out->ms[r.cls] += ms;
-        out->bytes[r.cls] += r.bytes;
-        out->launches[r.cls] += 1;
-      }
-    }
-    recs.clear();
-    used = 0;
-  }
-  ~KTimer() {
-    for (hipEvent_t e : pool) hipEventDestroy(e);
-  }
-};
-
-template <typename T> const T* links_as(const sk_operator* op);
-template <> const double2* links_as<double2>(const sk_operator* op) { return (const double2*)op->links; }
-template <> const float2* links_as<float2>(const sk_operator* op) { return (const float2*)op->links_c64; }
-
-#define SK_LAUNCH(call)                                                                   \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess) {                                                               \
-      ::sk::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, \
-                      __LINE__);                                                          \
-      return SK_ERR_HIP;                                                                  \
-    }                                                                                     \
-  } while (0)
-
-// k Arnoldi steps on the unnormalised basis in w.W; W_0 and scale[0] must be
-// set.  Kernels after a breakdown return at once (skip flag).
-template <typename T>
-int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int k, int adjoint,
-                    hipStream_t s, KTimer* tm = nullptr) {
-  const ArnoldiDev a = arn_of(w, k);
-  const T* U = links_as<T>(op);
-  const int* skip = &w.st->breakdown;
-  KTimer dummy;
-  KTimer& t = tm ? *tm : dummy;
-  const double c = (double)sizeof(T), nn = (double)n;
-  const int nrb = gs_row_blocks(n);
-  for (int j = 0; j < k; ++j) {
-    T* wj1 = w.W + (size_t)(j + 1) * n;
-    ScaleSrc src;
-    std::memset(&src, 0, sizeof(src));
-    src.arn = a;
-    src.nrb = nrb;
-    if (j == 0) {
-      src.in_scale = w.scale;
-    } else {
-      src.norm_part = w.norm_part;
-      src.jprev = j - 1;
-    }
-    // stencil: 12 in + 36 link + 12 out complex per site = 5 n complex
-    t.begin(SK_K_STENCIL, 5.0 * nn * c);
-    SK_LAUNCH((launch_wilson_arnoldi<T, T, T>(op, U, w.W + (size_t)j * n, wj1, adjoint, src, skip, s)));
-    t.end();
-    t.begin(SK_K_GS_DOT, (j + 2) * nn * c);
-    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, true, w.gpart, skip, s)));
-    t.end();
-    t.begin(SK_K_GS_UPD_DOT, (2 * j + 4) * nn * c);
-    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 1, w.gpart, a, w.norm_part, skip, s)));
-    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, false, w.gpart, skip, s)));
-    t.end();
-    t.begin(SK_K_GS_UPD_NORM, (j + 3) * nn * c);
-    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 2, w.gpart, a, w.norm_part, skip, s)));
-    t.end();
-  }
-  SK_LAUNCH(gs_finish(w.norm_part, n, k - 1, a, skip, s));
-  return SK_OK;
-}
 
 std::mutex g_mu;
 

@@ -1,0 +1,79 @@
+"""GPU deflation eigensolver (Krylov-Schur on H_W^2) against the oracle:
+dense eigendecomposition on small lattices, the oracle's ARPACK eigenvalues
+stored for the 8^4 configuration, and full deflated solves."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import skinputs as si
+from skinputs.configs import CONFIGS
+from oracle import dirac, deflation, xstar, rational
+from tests.gpu_util import make_op, to_dev, from_dev, vecs_to_dev, rel, announce, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _dev_vecs_to_host(T, V):
+    return np.stack([from_dev(T[i], V) for i in range(T.shape[0])], axis=1)
+
+
+@pytest.mark.parametrize("dims,m", [((4, 4, 4, 4), 12), ((3, 4, 5, 6), 20)])
+def test_eigensolver_matches_dense_oracle(dims, m):
+    from paper_0910_2927_amd import api
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.5, 300 + V)
+    A = dirac.hw_dense(U, dims, 0.25, 0.3)
+    announce(f"eigensolve dims={dims} m={m}")
+    op = make_op(U, dims, 0.25, 0.3)
+    R, L, F, lam, st = api.deflation_eigensolve(op, m, nev_extra=16, tol=1e-12)
+    Ro, Lo, lamo, Fo = deflation.lr_dense(A, m)
+    # same eigenvalues (the set of the m nearest zero)
+    assert np.allclose(np.sort_complex(lam), np.sort_complex(lamo), rtol=0, atol=1e-10)
+    Rh, Lh = _dev_vecs_to_host(R, V), _dev_vecs_to_host(L, V)
+    # biorthogonality, invariance, and the same oblique projector as the oracle's
+    assert np.linalg.norm(Lh.conj().T @ Rh - np.eye(m)) < 1e-10
+    Tm = Rh.conj().T @ (A @ Rh)
+    assert np.linalg.norm(A @ Rh - Rh @ Tm) < 1e-9 * np.linalg.norm(A @ Rh)
+    b = si.gaussian_source(12 * V, 301)
+    Pb = Rh @ (Lh.conj().T @ b)
+    Pbo = Ro @ (Lo.conj().T @ b)
+    assert rel(Pb, Pbo) < 1e-9
+    # x_P = R F L^H b equals sign(A) P b
+    Fh = F.cpu().numpy()
+    assert rel(Rh @ (Fh @ (Lh.conj().T @ b)), xstar.x_p(b, Ro, Lo, Fo)) < 1e-9
+
+
+def test_eigensolver_config_c2_matches_stored_oracle_eigenvalues_and_solve():
+    """8^4, eps = 0.6, mu = 0.3, 20 deflated, 16 poles, k = 50: eigenvalues
+    against the oracle's ARPACK run and x against the oracle's x* at the
+    stored sample of components."""
+    from paper_0910_2927_amd import api
+    cfg = CONFIGS["c2"]
+    mu = 0.3
+    g = json.load(open(os.path.join(GOLDEN, f"c2_mu{mu:g}.json")))
+    U = si.gauge_links(cfg.dims, cfg.eps, si.seed_for(cfg.L, "gauge"))
+    b = si.gaussian_source(cfg.n, si.seed_for(cfg.L, "b"))
+    announce("eigensolve c2 8^4 m=20")
+    op = make_op(U, cfg.dims, cfg.kappa, mu)
+    R, L, F, lam, st = api.deflation_eigensolve(op, cfg.m, nev_extra=16, tol=1e-12)
+    print("eigensolver stats", st)
+    ref = np.array(g["eig_re"]) + 1j * np.array(g["eig_im"])
+    assert np.allclose(np.sort_complex(lam), np.sort_complex(ref), rtol=0, atol=1e-9)
+    c = cfg.scales[mu]
+    assert g["c"] == c
+    sig, om = api.kl_poles(cfg.s, c)
+    announce("sign_apply c2 8^4 with GPU deflation")
+    res = api.sign_apply(op, to_dev(b, cfg.V), sig, om, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles,
+                         R=R, Lv=L, F=F)
+    assert res.converged
+    idx = np.array(g["sample_index"])
+    x = from_dev(res.x, cfg.V)
+    xs = np.array(g["x_re"]) + 1j * np.array(g["x_im"])
+    err = rel(x[idx], xs)
+    print(f"c2 sampled rel err {err:.2e}, cycles {res.cycles}, |x| {np.linalg.norm(x):.6f} vs {g['x_norm']:.6f}")
+    assert err <= 1e-8
+    assert abs(np.linalg.norm(x) - g["x_norm"]) <= 1e-8 * g["x_norm"]
