@@ -82,6 +82,10 @@ typedef struct {
  */
 int kl_poles(int s, double c, double* sigma, double* omega);
 
+/* links_c64 = links rounded to complex float (device, 36 V entries each;
+   the operator's links_c64 for the complex-float stencil). */
+int sk_links_to_c64(const double* links, float* links_c64, int64_t V, hipStream_t stream);
+
 /* Number of lattice sites of an operator (0 if dims are invalid). */
 int64_t sk_volume(const sk_operator* op);
 
@@ -168,6 +172,11 @@ typedef struct {
   const double* F;          /* device, m x m complex double, f(Lambda) in basis R */
   int32_t project_each_cycle; /* 1: projection step after every cycle (Alg. 1) */
   int32_t precision;        /* sk_precision */
+  double mixed_switch;      /* SK_PREC_MIXED: cycles run in complex double until the
+                               relative update ||sum omega_i y_i|| / ||x|| falls
+                               below this, then in complex float (complex-float
+                               rounding then only touches the small remaining
+                               error).  0 = 1e-3; >= 1 = complex float throughout. */
   double* X_shift;          /* device, N x n complex double, or NULL: per-shift
                                solutions of (A - sigma_i) X_i = (I - P) b */
 } sk_sign_params;
@@ -195,6 +204,7 @@ typedef struct {
 
 typedef struct {
   int32_t cycles;           /* restart cycles run */
+  int32_t cycles_c64;       /* of which with the complex-float basis */
   int32_t matvecs;          /* H_W applications (all precisions) */
   int32_t converged;        /* 1 if the stopping rule was met */
   int32_t breakdown;        /* 1 if a cycle ended in lucky breakdown */

@@ -43,7 +43,7 @@ class SkSignParams(C.Structure):
                 ("max_cycles", C.c_int32), ("tol", C.c_double), ("m", C.c_int32),
                 ("R", C.c_void_p), ("L", C.c_void_p), ("F", C.c_void_p),
                 ("project_each_cycle", C.c_int32), ("precision", C.c_int32),
-                ("X_shift", C.c_void_p)]
+                ("mixed_switch", C.c_double), ("X_shift", C.c_void_p)]
 
 
 SK_KERNEL_CLASSES = ["stencil", "gs_dot", "gs_upd_dot", "gs_upd_norm", "small", "sol_update",
@@ -55,7 +55,8 @@ class SkKernelTimes(C.Structure):
 
 
 class SkStats(C.Structure):
-    _fields_ = [("cycles", C.c_int32), ("matvecs", C.c_int32), ("converged", C.c_int32),
+    _fields_ = [("cycles", C.c_int32), ("cycles_c64", C.c_int32), ("matvecs", C.c_int32),
+                ("converged", C.c_int32),
                 ("breakdown", C.c_int32), ("final_update_norm", C.c_double),
                 ("x_norm", C.c_double), ("hist_update", C.POINTER(C.c_double)),
                 ("hist_beta", C.POINTER(C.c_double)), ("hist_leak", C.POINTER(C.c_double)),
@@ -76,6 +77,7 @@ class SkEigStats(C.Structure):
 SIGNATURES = [
     ("sk_volume", C.c_int64, [C.POINTER(SkOperator)]),
     ("kl_poles", C.c_int, [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("sk_links_to_c64", C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     ("sk_last_error", C.c_char_p, []),
     ("wilson_apply", C.c_int, [C.POINTER(SkOperator), C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                C.c_void_p]),

@@ -85,6 +85,14 @@ class WilsonOperator:
     def with_mu(self, mu):
         return WilsonOperator(self.links, self.dims, self.kappa, mu, self.antiperiodic_t, self.links64)
 
+    def ensure_c64(self):
+        """Create the complex-float copy of the links (library kernel)."""
+        if self.links64 is None:
+            lib = L.load()
+            self.links64 = torch.empty(36 * self.V, dtype=torch.complex64, device=self.device)
+            L.check(lib.sk_links_to_c64(_ptr(self.links), _ptr(self.links64), self.V, _stream()))
+        return self
+
 
 def kl_poles(s, c):
     """First-order poles/weights of the Kenney-Laub g_s(c x) (library routine)."""
@@ -215,6 +223,7 @@ class SignResult:
     x: torch.Tensor
     status: int
     cycles: int
+    cycles_c64: int
     matvecs: int
     converged: bool
     breakdown: bool
@@ -229,8 +238,12 @@ class SignSolver:
 
     def __init__(self, op: WilsonOperator, sigma, omega, k, tol=1e-9, max_cycles=500,
                  R=None, Lv=None, F=None, project_each_cycle=True, precision="fp64",
-                 keep_shift_solutions=False, hist_cap=4096):
+                 keep_shift_solutions=False, hist_cap=4096, mixed_switch=0.0):
         self.lib = L.load()
+        if precision in ("mixed", "mixed_c64_only"):
+            op.ensure_c64()
+            if precision == "mixed_c64_only":
+                mixed_switch = 1.0
         self.op = op
         self._sg, self.N = _cplx_host(sigma)
         self._om, _ = _cplx_host(omega)
@@ -256,7 +269,8 @@ class SignSolver:
         p.L = Lv.data_ptr() if self.m else None
         p.F = self.F.data_ptr() if self.m else None
         p.project_each_cycle = 1 if project_each_cycle else 0
-        p.precision = L.SK_PREC_MIXED if precision == "mixed" else L.SK_PREC_FP64
+        p.precision = L.SK_PREC_FP64 if precision == "fp64" else L.SK_PREC_MIXED
+        p.mixed_switch = float(mixed_switch)
         p.X_shift = self.X.data_ptr() if self.X is not None else None
         self.params = p
         self.opstruct = op.struct()
@@ -283,7 +297,8 @@ class SignSolver:
         if raise_on_error and status not in (L.SK_OK,):
             L.check(status)
         nc = min(st.cycles, self.hist_cap)
-        return SignResult(x=x, status=status, cycles=st.cycles, matvecs=st.matvecs,
+        return SignResult(x=x, status=status, cycles=st.cycles, cycles_c64=st.cycles_c64,
+                          matvecs=st.matvecs,
                           converged=bool(st.converged), breakdown=bool(st.breakdown),
                           update_norms=np.array(self._hu[:nc]), betas=np.array(self._hb[:nc]),
                           leaks=np.array(self._hl[:nc]), X_shift=self.X)

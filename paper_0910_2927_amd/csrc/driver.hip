@@ -356,11 +356,7 @@ int deflate_project(int m, int64_t n, const double* R, const double* L, const do
 namespace sk {
 namespace {
 
-struct SignWs {
-  size_t bytes;
-};
-
-bool params_ok(const sk_sign_params* p, int64_t n, char* msg, size_t len) {
+bool params_ok(const sk_sign_params* p, char* msg, size_t len) {
   if (!p) return snprintf(msg, len, "params are NULL"), false;
   if (p->npoles < 1 || p->npoles > kMaxPoles) return snprintf(msg, len, "npoles = %d outside [1, %d]", p->npoles, kMaxPoles), false;
   if (!p->sigma || !p->omega) return snprintf(msg, len, "sigma/omega are NULL"), false;
@@ -370,18 +366,94 @@ bool params_ok(const sk_sign_params* p, int64_t n, char* msg, size_t len) {
   if (p->m < 0 || p->m > kMaxDefl) return snprintf(msg, len, "m = %d outside [0, %d]", p->m, kMaxDefl), false;
   if (p->m > 0 && (!p->R || !p->L || !p->F)) return snprintf(msg, len, "m > 0 needs R, L and F"), false;
   if (p->precision != SK_PREC_FP64 && p->precision != SK_PREC_MIXED) return snprintf(msg, len, "unknown precision %d", p->precision), false;
-  (void)n;
+  if (!(p->mixed_switch >= 0.0)) return snprintf(msg, len, "mixed_switch must be >= 0"), false;
   return true;
 }
 
-template <typename T>
-size_t sign_ws_bytes(int64_t n, const sk_sign_params* p) {
-  Carver c;
-  KrylovWs<T> w;
-  return carve_krylov(c, w, n, p->k, p->npoles, p->m, p->X_shift != nullptr);
+// Two views of one workspace: the complex-double basis and, for the mixed
+// path, a complex-float basis; every other array is shared.
+struct SignWs {
+  KrylovWs<double2> w64;
+  KrylovWs<float2> w32;
+  bool mixed;
+};
+
+size_t carve_sign(Carver& c, SignWs& sw, int64_t n, const sk_sign_params* p) {
+  sw.mixed = p->precision == SK_PREC_MIXED;
+  carve_krylov(c, sw.w64, n, p->k, p->npoles, p->m, p->X_shift != nullptr);
+  std::memcpy(&sw.w32, &sw.w64, sizeof(sw.w32));   // same small arrays
+  sw.w32.W = sw.mixed ? c.take<float2>((size_t)(p->k + 1) * n) : nullptr;
+  return c.off;
 }
 
-template <typename T>
+template <typename T> KrylovWs<T>& view(SignWs& sw);
+template <> KrylovWs<double2>& view<double2>(SignWs& sw) { return sw.w64; }
+template <> KrylovWs<float2>& view<float2>(SignWs& sw) { return sw.w32; }
+
+struct CycleArgs {
+  const sk_operator* op;
+  const sk_sign_params* p;
+  int64_t n;
+  const PoleSet* ps;
+  double2* x;
+  double2* X;
+  KTimer* tm;
+  hipStream_t s;
+};
+
+// One restart cycle of Algorithm 1 with the basis in precision T; the
+// restart vector goes to W_0 of the next cycle's precision TN.
+template <typename T, typename TN>
+int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
+  KrylovWs<T>& w = view<T>(sw);
+  KrylovWs<TN>& wn = view<TN>(sw);
+  const int64_t n = ca.n;
+  const int k = ca.p->k, m = ca.p->m, N = ca.ps->n;
+  const ArnoldiDev a = arn_of(w, k);
+  const int cs = ts_counter_stride(n);
+  const int* skip = &w.st->breakdown;
+  KTimer& tm = *ca.tm;
+  const double cb = (double)sizeof(T), nn = (double)n;
+  const double2* R = (const double2*)ca.p->R;
+  const double2* Lv = (const double2*)ca.p->L;
+  SK_TRY(enqueue_arnoldi<T>(ca.op, w, n, k, 0, ca.s, &tm));
+  tm.begin(SK_K_SMALL, 0.0);
+  SK_LAUNCH(launch_fom_small(a, k, *ca.ps, w.rho, w.Y, w.U, w.ucoef, ca.X ? w.ycoef : nullptr, ca.s));
+  tm.end();
+  TsEpiArgs ex = epi_of(EPI_XNORM, a);
+  ex.dst_scalar = &w.st->xnorm2;
+  tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * nn * 16.0);
+  SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, ca.x, n, true, 2, ex, w.partial, w.counter + 6 * cs,
+                        &w.st->kdone, nullptr, ca.s)));
+  tm.end();
+  if (ca.X) {
+    tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * N * nn * 16.0);
+    SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, ca.X, n, &w.st->kdone, ca.s)));
+    tm.end();
+  }
+  // r = v_{k+1};  r = (I - P) r  (projection step)
+  T* Wk = w.W + (size_t)k * n;
+  TsEpiArgs eb = epi_of(EPI_BETA, a);
+  eb.dst_scalar = &w.st->beta;
+  eb.dst_scale = w.scale;
+  if (m > 0) {
+    TsEpiArgs ed = epi_of(EPI_DEFL, a);
+    ed.out = w.dc;
+    ed.alpha = w.scale + k;
+    ed.dst_scalar = &w.st->leak;
+    tm.begin(SK_K_PROJECT, m * nn * 16.0 + nn * cb);
+    SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7 * cs, skip, ca.s)));
+    tm.end();
+  }
+  const bool proj = m > 0 && ca.p->project_each_cycle;
+  tm.begin(SK_K_PROJECT, (proj ? m * nn * 16.0 : 0.0) + nn * cb + nn * (double)sizeof(TN));
+  SK_LAUNCH((ts_update<double2, T, TN>(proj ? R : (const double2*)nullptr, n, proj ? m : 0, w.dc,
+                                       w.scale + k, Wk, wn.W, n, 2, eb, w.partial, w.counter + 8 * cs,
+                                       skip, ca.s)));
+  tm.end();
+  return SK_OK;
+}
+
 int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, double2* x,
               sk_stats* stats, void* ws, hipStream_t s) {
   const int64_t n = 12 * volume_of(op);
@@ -391,12 +463,15 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   const double2* Lv = (const double2*)p->L;
   Carver c;
   c.base = (char*)ws;
-  KrylovWs<T> w;
-  carve_krylov(c, w, n, k, N, m, X != nullptr);
+  SignWs sw;
+  carve_sign(c, sw, n, p);
+  KrylovWs<double2>& w = sw.w64;
   PoleSet ps;
   SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
   const ArnoldiDev a = arn_of(w, k);
   const int cs = ts_counter_stride(n);
+  const double theta = !sw.mixed ? 0.0 : (p->mixed_switch > 0.0 ? p->mixed_switch : 1e-3);
+  bool low = sw.mixed && theta >= 1.0;   // precision of the current cycle
 
   SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, kCounterSlots * cs, s));
   SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(k + 1) * k * 2, s));
@@ -416,18 +491,23 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
                                         nullptr, s)));
     SK_LAUNCH((ts_gemv<double2>(R, n, m, w.dc2, x, n, false, 0, e0, nullptr, nullptr, nullptr,
                                 nullptr, s)));
-    SK_LAUNCH((ts_update<double2, double2, T>(R, n, m, w.dc, nullptr, b, w.W, n, 2, eb, w.partial,
-                                              w.counter + 5 * cs, nullptr, s)));
   } else {
     SK_LAUNCH(launch_fill_zero((double*)x, n * 2, s));
-    SK_LAUNCH((ts_update<double2, double2, T>((const double2*)nullptr, n, 0, nullptr, nullptr, b,
-                                              w.W, n, 2, eb, w.partial, w.counter + 5 * cs, nullptr, s)));
   }
+  if (low)
+    SK_LAUNCH((ts_update<double2, double2, float2>(m > 0 ? R : nullptr, n, m, w.dc, nullptr, b,
+                                                   sw.w32.W, n, 2, eb, w.partial, w.counter + 5 * cs,
+                                                   nullptr, s)));
+  else
+    SK_LAUNCH((ts_update<double2, double2, double2>(m > 0 ? R : nullptr, n, m, w.dc, nullptr, b, w.W,
+                                                    n, 2, eb, w.partial, w.counter + 5 * cs, nullptr,
+                                                    s)));
   CycleState hs;
   SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   SK_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->cycles = 0;
+    stats->cycles_c64 = 0;
     stats->matvecs = 0;
     stats->converged = 0;
     stats->breakdown = 0;
@@ -442,59 +522,30 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     if (stats) stats->converged = 1;
     return SK_OK;
   }
-  const int* skip = &w.st->breakdown;
-  T* Wk = w.W + (size_t)k * n;
-  int small = 0, status = SK_ERR_NOCONV;
-  double beta_cycle = hs.beta, first_upd = 0.0;
-  bool diverged = false;
   KTimer tm;
   if (stats && stats->times) {
     tm.out = stats->times;
     tm.s = s;
   }
-  const double cb = (double)sizeof(T), nn = (double)n;
+  CycleArgs ca{op, p, n, &ps, x, X, &tm, s};
+  int small = 0, status = SK_ERR_NOCONV;
+  double beta_cycle = hs.beta, first_upd = 0.0;
+  bool diverged = false;
   for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
-    SK_TRY(enqueue_arnoldi<T>(op, w, n, k, 0, s, &tm));
-    tm.begin(SK_K_SMALL, 0.0);
-    SK_LAUNCH(launch_fom_small(a, k, ps, w.rho, w.Y, w.U, w.ucoef, X ? w.ycoef : nullptr, s));
-    tm.end();
-    TsEpiArgs ex = epi_of(EPI_XNORM, a);
-    ex.dst_scalar = &w.st->xnorm2;
-    tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * nn * 16.0);
-    SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, x, n, true, 2, ex, w.partial, w.counter + 6 * cs,
-                          &w.st->kdone, nullptr, s)));
-    tm.end();
-    if (X) {
-      tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * N * nn * 16.0);
-      SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, X, n, &w.st->kdone, s)));
-      tm.end();
-    }
-    // r = v_{k+1};  r = (I - P) r  (projection step)
-    if (m > 0) {
-      TsEpiArgs ed = epi_of(EPI_DEFL, a);
-      ed.out = w.dc;
-      ed.alpha = w.scale + k;
-      ed.dst_scalar = &w.st->leak;
-      tm.begin(SK_K_PROJECT, m * nn * 16.0 + nn * cb);
-      SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7 * cs, skip, s)));
-      tm.end();
-    }
-    if (m > 0 && p->project_each_cycle) {
-      tm.begin(SK_K_PROJECT, m * nn * 16.0 + 2.0 * nn * cb);
-      SK_LAUNCH((ts_update<double2, T, T>(R, n, m, w.dc, w.scale + k, Wk, w.W, n, 2, eb, w.partial,
-                                          w.counter + 8 * cs, skip, s)));
-      tm.end();
-    } else {
-      tm.begin(SK_K_PROJECT, 2.0 * nn * cb);
-      SK_LAUNCH((ts_update<T, T, T>((const T*)nullptr, n, 0, nullptr, w.scale + k, Wk, w.W, n, 2, eb,
-                                    w.partial, w.counter + 8 * cs, skip, s)));
-      tm.end();
-    }
+    // the next cycle's precision is decided before this one is enqueued:
+    // once low, it stays low
+    const bool low_next = low || (sw.mixed && cyc > 0 && hs.upd_norm <= theta * std::sqrt(hs.xnorm2));
+    const bool cur = low;
+    if (!cur && !low_next) SK_TRY((enqueue_cycle<double2, double2>(ca, sw)));
+    else if (!cur && low_next) SK_TRY((enqueue_cycle<double2, float2>(ca, sw)));
+    else SK_TRY((enqueue_cycle<float2, float2>(ca, sw)));
+    low = low_next;
     SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     SK_HIP(hipStreamSynchronize(s));
     tm.flush();
     if (stats) {
       stats->cycles = cyc + 1;
+      stats->cycles_c64 += cur ? 1 : 0;
       stats->matvecs += hs.kdone;
       stats->final_update_norm = hs.upd_norm;
       stats->x_norm = std::sqrt(hs.xnorm2);
@@ -531,7 +582,6 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     else if (hs.upd_norm > kDivergeFactor * first_upd) {
       set_error("restarted FOM diverged (cycle %d, update %.3e): try another restart length",
                 cyc + 1, hs.upd_norm);
-      status = SK_ERR_NOCONV;
       diverged = true;
       break;
     }
@@ -549,20 +599,19 @@ extern "C" {
 size_t sign_apply_workspace_bytes(const sk_operator* op, const sk_sign_params* p) {
   if (!op || !p || volume_of(op) <= 0) return 0;
   char msg[256];
-  const int64_t n = 12 * volume_of(op);
-  if (!params_ok(p, n, msg, sizeof msg)) return 0;
-  if (p->precision == SK_PREC_MIXED) return sign_ws_bytes<float2>(n, p);
-  return sign_ws_bytes<double2>(n, p);
+  if (!params_ok(p, msg, sizeof msg)) return 0;
+  Carver c;
+  SignWs sw;
+  return carve_sign(c, sw, 12 * volume_of(op), p);
 }
 
 int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, double* x,
                sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
-  const sk_dtype dt = (p && p->precision == SK_PREC_MIXED) ? SK_C64 : SK_C128;
   SK_TRY(check_operator(op, SK_C128));
-  if (dt == SK_C64) SK_TRY(check_operator(op, SK_C64));
+  if (p && p->precision == SK_PREC_MIXED) SK_TRY(check_operator(op, SK_C64));
   const int64_t n = 12 * volume_of(op);
   char msg[256];
-  SK_CHECK(params_ok(p, n, msg, sizeof msg), "%s", msg);
+  SK_CHECK(params_ok(p, msg, sizeof msg), "%s", msg);
   SK_CHECK(b && x && ws, "b, x and ws must be non-NULL");
   SK_CHECK(!overlap(b, n * 16, x, n * 16), "b and x overlap");
   if (p->X_shift)
@@ -575,11 +624,15 @@ int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, 
     return SK_ERR_WORKSPACE;
   }
   SK_CHECK(!overlap(ws, need, x, n * 16) && !overlap(ws, need, b, n * 16), "workspace overlaps b or x");
-  if (p->precision == SK_PREC_MIXED) {
-    set_error("mixed precision is not available in this build");
-    return SK_ERR_ARG;
-  }
-  return sign_impl<double2>(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
+  return sign_impl(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
+}
+
+int sk_links_to_c64(const double* links, float* links_c64, int64_t V, hipStream_t stream) {
+  SK_CHECK(links && links_c64 && V >= 1, "bad arguments");
+  SK_CHECK(!overlap(links, 36 * V * 16, links_c64, 36 * V * 8), "buffers overlap");
+  SK_LAUNCH((ts_scale<double2, float2>((const double2*)links, (float2*)links_c64, 36 * V, nullptr, 1.0,
+                                       stream)));
+  return SK_OK;
 }
 
 }  // extern "C"
