@@ -230,6 +230,25 @@ int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, 
                sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Gradient of F = Re <eta, g(H_W) b>, g = sum_j omega_j / (x - sigma_j)
+ * (no deflation, p->m must be 0; complex double), with respect to the
+ * links, U_nu(x) -> exp(i theta^a lambda_a / 2) U_nu(x) at theta = 0, and to mu:
+ *   dF = -Re sum_j omega_j z_j^H (dH_W) x_j,
+ *   x_j = (H_W - sigma_j)^{-1} b,  z_j = (H_W^H - conj sigma_j)^{-1} eta,
+ * the z_j from the same restarted multishift FOM on H_W^H = H_W(-mu).
+ *   x_out: device, n complex double, nullable: g(H_W) b (the forward result)
+ *   grad_theta: device, double [4][V][8] (direction nu, site, generator a)
+ *   grad_mu: host, one double.
+ *   stats: host, nullable, two entries (forward solve, adjoint solve).
+ * ws: sign_apply_backward_workspace_bytes (holds both sets of per-shift
+ * solutions, 2 N n complex doubles).
+ */
+size_t sign_apply_backward_workspace_bytes(const sk_operator* op, const sk_sign_params* p);
+int sign_apply_backward(const sk_operator* op, const sk_sign_params* p, const double* b,
+                        const double* eta, double* x_out, double* grad_theta, double* grad_mu,
+                        sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * Deflation data for Algorithm 1: the m "critical" eigenvalues of H_W
  * (Sect. 4 -- the paper takes R_m, L_m, Lambda_m as given inputs).
  * Krylov-Schur (thick-restart Arnoldi) on A^2 for its eigenvalues of

@@ -307,3 +307,55 @@ class SignSolver:
 def sign_apply(op, b, sigma, omega, k, **kw):
     return SignSolver(op, sigma, omega, k, **{k_: v for k_, v in kw.items() if k_ != "raise_on_error"})(
         b, raise_on_error=kw.get("raise_on_error", True))
+
+
+def sign_apply_backward(op: WilsonOperator, b, eta, sigma, omega, k, tol=1e-12, max_cycles=1000):
+    """Gradient of F = Re <eta, g(H_W) b> (no deflation, complex double).
+
+    Returns (x = g(H_W) b, grad_theta (4, V, 8) float64, dF/dmu)."""
+    lib = L.load()
+    solver = SignSolver(op, sigma, omega, k, tol=tol, max_cycles=max_cycles)
+    p = solver.params
+    s = op.struct()
+    nb = lib.sign_apply_backward_workspace_bytes(C.byref(s), C.byref(p))
+    if nb == 0:
+        raise SkError(L.SK_ERR_ARG, "invalid parameters for sign_apply_backward")
+    ws = _workspace(nb, op.device)
+    _need(b, torch.complex128, op.n, "b")
+    _need(eta, torch.complex128, op.n, "eta")
+    x = torch.empty_like(b)
+    grad = torch.empty((4, op.V, 8), dtype=torch.float64, device=op.device)
+    gmu = C.c_double(0.0)
+    st = (L.SkStats * 2)()
+    L.check(lib.sign_apply_backward(C.byref(s), C.byref(p), _ptr(b), _ptr(eta), _ptr(x), _ptr(grad),
+                                    C.byref(gmu), st, _ptr(ws), ws.numel(), _stream()))
+    return x, grad, gmu.value
+
+
+class SignKrylov(torch.autograd.Function):
+    """x = g(H_W(U, mu)) b with gradients for the links and mu.
+
+    ``theta`` is the (4, V, 8) real tangent coordinate of the links at the
+    current field (U -> exp(i theta^a lambda_a/2) U, evaluated at theta = 0,
+    so pass zeros); ``mu`` a 0-dim float64 tensor.  For a real loss L the
+    incoming gradient of the complex output is dL/dRe x + i dL/dIm x = eta,
+    and L changes by Re <eta, dx>, which is what the library differentiates."""
+
+    @staticmethod
+    def forward(ctx, theta, mu, b, op, sigma, omega, k, tol, max_cycles):
+        if theta.abs().max().item() != 0.0:
+            raise ValueError("theta is a tangent coordinate at the current links: pass zeros")
+        opm = op.with_mu(float(mu))
+        res = SignSolver(opm, sigma, omega, k, tol=tol, max_cycles=max_cycles)(b)
+        ctx.save_for_backward(b)
+        ctx.cfg = (opm, sigma, omega, k, tol, max_cycles)
+        return res.x
+
+    @staticmethod
+    def backward(ctx, grad_x):
+        (b,) = ctx.saved_tensors
+        opm, sigma, omega, k, tol, max_cycles = ctx.cfg
+        _, g, gmu = sign_apply_backward(opm, b, grad_x.contiguous().to(torch.complex128), sigma, omega,
+                                        k, tol=tol, max_cycles=max_cycles)
+        return g, torch.tensor(gmu, dtype=torch.float64, device=g.device), None, None, None, None, \
+            None, None, None

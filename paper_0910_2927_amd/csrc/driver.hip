@@ -627,6 +627,81 @@ int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, 
   return sign_impl(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
 }
 
+size_t sign_apply_backward_workspace_bytes(const sk_operator* op, const sk_sign_params* p) {
+  if (!op || !p || volume_of(op) <= 0 || p->m != 0 || p->precision != SK_PREC_FP64) return 0;
+  char msg[256];
+  if (!params_ok(p, msg, sizeof msg)) return 0;
+  const int64_t n = 12 * volume_of(op);
+  sk_sign_params q = *p;
+  q.X_shift = (double*)16;   // sized with per-shift solutions
+  Carver c;
+  SignWs sw;
+  carve_sign(c, sw, n, &q);
+  c.take<double2>((size_t)2 * p->npoles * n);     // X, Z
+  c.take<double2>(n);                              // scratch for the adjoint result
+  c.take<double>(grad_blocks(volume_of(op)));      // mu partials
+  return c.off;
+}
+
+int sign_apply_backward(const sk_operator* op, const sk_sign_params* p, const double* b,
+                        const double* eta, double* x_out, double* grad_theta, double* grad_mu,
+                        sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream) {
+  SK_TRY(check_operator(op, SK_C128));
+  char msg[256];
+  SK_CHECK(params_ok(p, msg, sizeof msg), "%s", msg);
+  SK_CHECK(p->m == 0, "the gradient is defined without deflation (m must be 0)");
+  SK_CHECK(p->precision == SK_PREC_FP64, "the gradient runs in complex double");
+  SK_CHECK(b && eta && grad_theta && grad_mu && ws, "NULL argument");
+  const int64_t n = 12 * volume_of(op), V = volume_of(op);
+  const size_t need = sign_apply_backward_workspace_bytes(op, p);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  SK_CHECK(!overlap(grad_theta, 32 * V * 8, ws, need), "grad_theta overlaps the workspace");
+  const int N = p->npoles;
+  sk_sign_params q = *p;
+  q.X_shift = (double*)16;
+  Carver c;
+  c.base = (char*)ws;
+  SignWs sw;
+  carve_sign(c, sw, n, &q);
+  const size_t solver_bytes = c.off;
+  double2* X = c.take<double2>((size_t)N * n);
+  double2* Z = c.take<double2>((size_t)N * n);
+  double2* xa = c.take<double2>(n);
+  double* mu_part = c.take<double>(grad_blocks(V));
+  // forward: x_j = (H - sigma_j)^{-1} b
+  q.X_shift = (double*)X;
+  double2* xf = x_out ? (double2*)x_out : xa;
+  SK_TRY(sign_impl(op, &q, (const double2*)b, xf, stats ? &stats[0] : nullptr, ws, stream));
+  // adjoint: z_j = (H(-mu) - conj sigma_j)^{-1} eta
+  sk_operator opa = *op;
+  opa.mu = -op->mu;
+  std::vector<double> sg(2 * N), om(2 * N);
+  for (int i = 0; i < N; ++i) {
+    sg[2 * i] = p->sigma[2 * i];
+    sg[2 * i + 1] = -p->sigma[2 * i + 1];
+    om[2 * i] = p->omega[2 * i];
+    om[2 * i + 1] = -p->omega[2 * i + 1];
+  }
+  q.sigma = sg.data();
+  q.omega = om.data();
+  q.X_shift = (double*)Z;
+  SK_TRY(sign_impl(&opa, &q, (const double2*)eta, xa, stats ? &stats[1] : nullptr, ws, stream));
+  (void)solver_bytes;
+  PoleSet ps;
+  SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
+  SK_LAUNCH(launch_grad(op, ps, X, Z, grad_theta, mu_part, stream));
+  std::vector<double> mp(grad_blocks(V));
+  SK_HIP(hipMemcpyAsync(mp.data(), mu_part, mp.size() * sizeof(double), hipMemcpyDeviceToHost, stream));
+  SK_HIP(hipStreamSynchronize(stream));
+  double acc = 0.0;
+  for (double v : mp) acc += v;
+  *grad_mu = acc;
+  return SK_OK;
+}
+
 int sk_links_to_c64(const double* links, float* links_c64, int64_t V, hipStream_t stream) {
   SK_CHECK(links && links_c64 && V >= 1, "bad arguments");
   SK_CHECK(!overlap(links, 36 * V * 16, links_c64, 36 * V * 8), "buffers overlap");

@@ -186,6 +186,11 @@ hipError_t launch_fom_small(const ArnoldiDev& arn, int k, const PoleSet& poles,
                             double2* rho, double2* Y, double2* U, double2* ucoef,
                             double2* ycoef, hipStream_t s);
 
+// Link and mu gradient of Re<eta, g(H) b> from per-shift solutions (backward.hip).
+int grad_blocks(int64_t V);
+hipError_t launch_grad(const sk_operator* op, const PoleSet& ps, const double2* X, const double2* Z,
+                       double* grad, double* mu_part, hipStream_t s);
+
 hipError_t launch_zero_counters(unsigned* counter, int n, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t count, hipStream_t s);
 

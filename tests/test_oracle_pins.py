@@ -348,3 +348,32 @@ def test_unrestarted_multishift_fom_matches_dense():
     ref, Xref = xstar.xstar_dense(A.toarray(), b, sig, om, return_shifts=True)
     assert rel(x, ref) < 1e-11
     assert rel(X, Xref) < 1e-11
+
+
+# ---------------------------------------------------------------- gradient
+def test_oracle_gradient_matches_finite_differences_2x4():
+    """The dense gradient formula against central differences of F with
+    exponentiated links, on coordinates of every direction, and dF/dmu
+    against a central difference in mu."""
+    from oracle import gradient
+    dims = (2, 2, 2, 2)
+    V = 16
+    U = si.gauge_links(dims, 0.5, 500)
+    b = si.gaussian_source(12 * V, 501)
+    eta = si.gaussian_source(12 * V, 502)
+    sig, om = rational.kl_first_order(4, 1.2)
+    coords = [(0, 3, 0), (1, 7, 1), (2, 11, 4), (3, 0, 7), (3, 15, 2), (0, 9, 6)]
+    grad, gmu = gradient.dense_gradient(U, dims, 0.25, 0.3, b, eta, sig, om, coords=coords)
+    for c in coords:
+        fd = gradient.fd_link(U, dims, 0.25, 0.3, b, eta, sig, om, *c, h=1e-5)
+        assert abs(fd - grad[c]) <= 1e-7 * max(1.0, abs(fd)), (c, fd, grad[c])
+    h = 1e-5
+    fdmu = (gradient.objective(U, dims, 0.25, 0.3 + h, b, eta, sig, om)
+            - gradient.objective(U, dims, 0.25, 0.3 - h, b, eta, sig, om)) / (2 * h)
+    assert abs(fdmu - gmu) <= 1e-7 * max(1.0, abs(fdmu))
+    # the directional form agrees with the coordinate gradient
+    theta = np.zeros((4, V, 8))
+    for c in coords:
+        theta[c] = 0.7 + 0.1 * c[2]
+    dd = gradient.directional_dense(U, dims, 0.25, 0.3, b, eta, sig, om, theta)
+    assert abs(dd - sum(theta[c] * grad[c] for c in coords)) < 1e-10 * max(1, abs(dd))
