@@ -454,6 +454,65 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   return SK_OK;
 }
 
+// A stream that belongs to the library, used only to capture restart cycles
+// into HIP graphs (the caller's stream may be the legacy null stream, which
+// cannot be captured).  Default priority.
+hipStream_t capture_stream() {
+  static hipStream_t cs = nullptr;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!cs) {
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) cs = nullptr;
+  }
+  return cs;
+}
+
+// The three kinds of restart cycle (basis precision now -> next), each
+// captured once per solve and replayed every cycle.
+struct CycleGraphs {
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  ~CycleGraphs() {
+    for (auto& e : exec)
+      if (e) hipGraphExecDestroy(e);
+  }
+};
+
+int enqueue_cycle_kind(int kind, const CycleArgs& ca, SignWs& sw) {
+  if (kind == 0) return enqueue_cycle<double2, double2>(ca, sw);
+  if (kind == 1) return enqueue_cycle<double2, float2>(ca, sw);
+  return enqueue_cycle<float2, float2>(ca, sw);
+}
+
+int run_cycle(int kind, const CycleArgs& ca, SignWs& sw, CycleGraphs& g, bool use_graph) {
+  if (!use_graph) return enqueue_cycle_kind(kind, ca, sw);
+  if (!g.exec[kind]) {
+    hipStream_t cs = capture_stream();
+    if (!cs) return enqueue_cycle_kind(kind, ca, sw);
+    CycleArgs cc = ca;
+    cc.s = cs;
+    SK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int st = enqueue_cycle_kind(kind, cc, sw);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (st != SK_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) {
+      set_error("graph capture failed: %s", hipGetErrorString(e));
+      return SK_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&g.exec[kind], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      g.exec[kind] = nullptr;
+      set_error("graph instantiation failed: %s", hipGetErrorString(e));
+      return SK_ERR_HIP;
+    }
+  }
+  SK_HIP(hipGraphLaunch(g.exec[kind], ca.s));
+  return SK_OK;
+}
+
 int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, double2* x,
               sk_stats* stats, void* ws, hipStream_t s) {
   const int64_t n = 12 * volume_of(op);
@@ -528,6 +587,8 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     tm.s = s;
   }
   CycleArgs ca{op, p, n, &ps, x, X, &tm, s};
+  CycleGraphs graphs;
+  const bool use_graph = !tm.on();   // per-kernel timing needs plain launches
   int small = 0, status = SK_ERR_NOCONV;
   double beta_cycle = hs.beta, first_upd = 0.0;
   bool diverged = false;
@@ -536,9 +597,7 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     // once low, it stays low
     const bool low_next = low || (sw.mixed && cyc > 0 && hs.upd_norm <= theta * std::sqrt(hs.xnorm2));
     const bool cur = low;
-    if (!cur && !low_next) SK_TRY((enqueue_cycle<double2, double2>(ca, sw)));
-    else if (!cur && low_next) SK_TRY((enqueue_cycle<double2, float2>(ca, sw)));
-    else SK_TRY((enqueue_cycle<float2, float2>(ca, sw)));
+    SK_TRY(run_cycle(!cur ? (low_next ? 1 : 0) : 2, ca, sw, graphs, use_graph));
     low = low_next;
     SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     SK_HIP(hipStreamSynchronize(s));

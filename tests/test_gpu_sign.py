@@ -164,3 +164,35 @@ def test_zero_source_and_deterministic_repeat():
     r1 = api.sign_apply(op, to_dev(b, V), sig, om, 8, tol=1e-10)
     r2 = api.sign_apply(op, to_dev(b, V), sig, om, 8, tol=1e-10)
     assert bool((r1.x == r2.x).all())   # fixed reduction order: bitwise repeatable
+
+
+def test_graph_replay_matches_plain_launches():
+    """Every restart cycle replays a captured HIP graph; with per-kernel
+    timing on, the same cycles run as plain launches.  Both must give the
+    same iterate bit for bit, in FP64 and in mixed precision (three graph
+    kinds: double->double, double->float, float->float)."""
+    import ctypes as C
+    import torch
+    from paper_0910_2927_amd import api, _lib
+    dims = (3, 4, 5, 6)
+    V, U, b, A = _problem(dims, 0.6, 0.3, 120, 121)
+    sig, om = rational.kl_first_order(8, 1.5)
+    op = make_op(U, dims, 0.25, 0.3)
+    lib = _lib.load()
+    for prec in ("fp64", "mixed"):
+        announce(f"graph vs plain launches {prec}")
+        solver = api.SignSolver(op, sig, om, 20, tol=1e-11, max_cycles=400, precision=prec)
+        bd = to_dev(b, V)
+        r1 = solver(bd)
+        x1 = r1.x.clone()
+        times = _lib.SkKernelTimes()
+        st = _lib.SkStats()
+        st.times = C.pointer(times)
+        x2 = torch.empty_like(bd)
+        s = lib.sign_apply(C.byref(solver.opstruct), C.byref(solver.params), C.c_void_p(bd.data_ptr()),
+                           C.c_void_p(x2.data_ptr()), C.byref(st), C.c_void_p(solver.ws.data_ptr()),
+                           solver.ws.numel(), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert s == 0 and st.cycles == r1.cycles and st.cycles_c64 == r1.cycles_c64
+        assert bool((x1 == x2).all())
+        if prec == "mixed":
+            assert 0 < r1.cycles_c64 < r1.cycles
