@@ -96,8 +96,7 @@ static size_t carve_arnoldi(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
   w.counter = c.template take<unsigned>((size_t)kCounterSlots * ts_counter_stride(n));
   w.st = c.template take<CycleState>(1);
   w.rho = c.template take<double2>(1);
-  w.gpart = c.template take<double2>((size_t)gs_row_blocks(n) * (k + 2));
-  w.norm_part = c.template take<double>(gs_row_blocks(n));
+  carve_gs(c, w, n, k);
   return c.off;
 }
 
@@ -129,13 +128,8 @@ static int arnoldi_impl(const sk_operator* op, T* V, double2* H, int k, int* k_d
   const int cs = ts_counter_stride(n);
   SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, kCounterSlots * cs, s));
   SK_LAUNCH(launch_fill_zero((double*)H, (int64_t)(k + 1) * k * 2, s));
-  // normalise the start vector: scale[0] = 1/||V_0||
-  TsEpiArgs eb = epi_of(EPI_BETA, a);
-  eb.dst_scalar = &w.st->beta;
-  eb.dst_scale = w.scale;
-  SK_LAUNCH((ts_dot<T, T>(V, n, 0, V, n, true, eb, w.partial, w.counter + 3 * cs, nullptr, s)));
+  (void)a;
   SK_TRY(enqueue_arnoldi<T>(op, w, n, k, 0, s));
-  SK_LAUNCH((ts_scale_basis<T>(V, n, k + 1, w.scale, &w.st->kdone, n, s)));
   CycleState hs;
   SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   SK_HIP(hipStreamSynchronize(s));
@@ -435,7 +429,7 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   T* Wk = w.W + (size_t)k * n;
   TsEpiArgs eb = epi_of(EPI_BETA, a);
   eb.dst_scalar = &w.st->beta;
-  eb.dst_scale = w.scale;
+  eb.dst_scale = w.scale + k + 1;   // unused slot: every stored v_j has unit norm
   if (m > 0) {
     TsEpiArgs ed = epi_of(EPI_DEFL, a);
     ed.out = w.dc;
@@ -534,10 +528,11 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
 
   SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, kCounterSlots * cs, s));
   SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(k + 1) * k * 2, s));
+  SK_LAUNCH(launch_fill_value(w.scale, k + 2, 1.0, s));   // the basis is stored normalised
   if (X) SK_LAUNCH(launch_fill_zero((double*)X, (int64_t)N * n * 2, s));
   TsEpiArgs eb = epi_of(EPI_BETA, a);
   eb.dst_scalar = &w.st->beta;
-  eb.dst_scale = w.scale;
+  eb.dst_scale = w.scale + k + 1;   // unused slot: every stored v_j has unit norm
   const TsEpiArgs e0 = epi_of(EPI_NONE, a);
   // x = x_P = R f(Lambda) L^H b ;  r = (I - P) b  (Algorithm 1, first two lines)
   if (m > 0) {

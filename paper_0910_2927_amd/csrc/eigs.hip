@@ -105,22 +105,20 @@ int krylov_schur(EigCtx& e, int adjoint, int nev, double tol, int max_restarts, 
   hipLaunchKernelGGL(k_start_vector, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w.W, n, seed);
   SK_LAUNCH(hipGetLastError());
   SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, kCounterSlots * cs, s));
-  TsEpiArgs eb = epi_of(EPI_BETA, a);
-  eb.dst_scalar = &w.st->beta;
-  eb.dst_scale = w.scale;
-  SK_LAUNCH((ts_dot<double2, double2>(w.W, n, 0, w.W, n, true, eb, w.partial, w.counter + 3 * cs,
-                                      nullptr, s)));
+  (void)a;
   int kk = 0;
   std::vector<cd> Tkk, bkk, Hd((size_t)(ncv + 1) * ncv), K, Q;
   CycleState hs;
   for (restarts = 0; restarts < max_restarts; ++restarts) {
     SK_LAUNCH(launch_init_state(w.st, w.rho, 0, w.counter, kCounterSlots * cs, s));
-    SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(ncv + 1) * ncv * 2, s));
+    // H starts as the restarted Rayleigh quotient [T_kk; b^T] in columns < kk
+    std::fill(Hd.begin(), Hd.end(), cd(0.0));
+    for (int j = 0; j < kk; ++j) {
+      for (int i = 0; i <= j; ++i) Hd[i + (size_t)j * (ncv + 1)] = Tkk[i + (size_t)j * kk];
+      Hd[kk + (size_t)j * (ncv + 1)] = bkk[j];
+    }
+    SK_TRY(to_dev(w.H, Hd, s));
     SK_TRY(enqueue_arnoldi<double2>(e.op, w, n, ncv, adjoint, s, nullptr, kk, 2, e.tmp));
-    // normalise every basis vector, then unit scales
-    SK_LAUNCH((ts_scale_basis<double2>(w.W, n, ncv + 1, w.scale, nullptr, n, s)));
-    hipLaunchKernelGGL(k_fill, dim3(2), dim3(256), 0, s, w.scale, (int64_t)(ncv + 2), 1.0);
-    SK_LAUNCH(hipGetLastError());
     SK_HIP(hipMemcpyAsync(Hd.data(), w.H, Hd.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
     SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     SK_HIP(hipStreamSynchronize(s));

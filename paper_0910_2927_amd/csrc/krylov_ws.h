@@ -45,9 +45,23 @@ struct KrylovWs {
   double2* ycoef;
   double2* dc;
   double2* dc2;
-  double2* gpart;      // CGS2 partial dots, gs_row_blocks(n) x (k+2)
+  double2* gpart;      // Gram-Schmidt partial dots, gs_row_blocks(n) x (2k+2)
   double* norm_part;   // partial ||w||^2, gs_row_blocks(n)
+  double2* sbuf;       // first-pass coefficients, 2 x (k+2) (alternating)
+  size_t gpart_cap;    // entries of gpart
+  int sbuf_k;          // k the first-pass buffers were sized for
 };
+
+// The Gram-Schmidt scratch of an Arnoldi run of length k (shared by every
+// workspace layout that runs enqueue_arnoldi).
+template <typename T>
+void carve_gs(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
+  w.gpart_cap = (size_t)gs_row_blocks(n) * (2 * k + 2);
+  w.gpart = c.template take<double2>(w.gpart_cap);
+  w.norm_part = c.template take<double>(gs_row_blocks(n));
+  w.sbuf = c.template take<double2>((size_t)2 * (k + 2));
+  w.sbuf_k = k;
+}
 
 template <typename T>
 size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int m, bool keep) {
@@ -67,8 +81,7 @@ size_t carve_krylov(Carver& c, KrylovWs<T>& w, int64_t n, int k, int npoles, int
   w.ycoef = keep ? c.template take<double2>((size_t)npoles * k) : nullptr;
   w.dc = c.template take<double2>(m > 0 ? m : 1);
   w.dc2 = c.template take<double2>(m > 0 ? m : 1);
-  w.gpart = c.template take<double2>((size_t)gs_row_blocks(n) * (k + 2));
-  w.norm_part = c.template take<double>(gs_row_blocks(n));
+  carve_gs(c, w, n, k);
   return c.off;
 }
 
@@ -162,10 +175,12 @@ template <> const float2* links_as<float2>(const sk_operator* op) { return (cons
 
 // k Arnoldi steps on the unnormalised basis in w.W; W_0 and scale[0] must be
 // set.  Kernels after a breakdown return at once (skip flag).
-// Arnoldi steps j = j0 .. k-1 on the unnormalised basis in w.W (W_{j0} and
-// scale[j0] set).  power = 2 applies the operator twice per step (A^2,
-// through `tmp`), as the deflation eigensolver needs.  Kernels after a
-// breakdown return at once (skip flag).
+// Arnoldi steps j = j0 .. k-1 on the basis in w.W, then the final second
+// pass of vector k (delayed reorthogonalisation, dcgs2.hip).  W_{j0} holds
+// the start vector (any norm when j0 = 0).  power = 2 applies the operator
+// twice per step (A^2, through `tmp`), as the deflation eigensolver needs;
+// j0 > 0 continues a thick-restarted decomposition whose columns < j0 are
+// already in H.  After a breakdown every later kernel returns at once.
 template <typename T>
 int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int k, int adjoint,
                     hipStream_t s, KTimer* tm = nullptr, int j0 = 0, int power = 1,
@@ -173,43 +188,43 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
   const ArnoldiDev a = arn_of(w, k);
   const T* U = links_as<T>(op);
   const int* skip = &w.st->breakdown;
+  // every buffer the step kernels index must be there and large enough
+  if (!w.W || !w.H || !w.st || !w.sbuf || !w.gpart || w.sbuf_k < k ||
+      w.gpart_cap < (size_t)gs_row_blocks(n) * (2 * k + 2) || (power == 2 && !tmp)) {
+    set_error("internal: Arnoldi workspace is missing a buffer or is too small");
+    return SK_ERR_WORKSPACE;
+  }
   KTimer dummy;
   KTimer& t = tm ? *tm : dummy;
   const double c = (double)sizeof(T), nn = (double)n;
-  const int nrb = gs_row_blocks(n);
+  auto sb = [&](int j) { return w.sbuf + (size_t)(j & 1) * (k + 2); };
   for (int j = j0; j < k; ++j) {
+    T* wj = w.W + (size_t)j * n;
     T* wj1 = w.W + (size_t)(j + 1) * n;
-    ScaleSrc src;
-    std::memset(&src, 0, sizeof(src));
-    src.arn = a;
-    src.nrb = nrb;
-    if (j == j0) {
-      src.in_scale = w.scale + j0;
-    } else {
-      src.norm_part = w.norm_part;
-      src.jprev = j - 1;
-    }
     // stencil: 12 in + 36 link + 12 out complex per site = 5 n complex
     t.begin(SK_K_STENCIL, 5.0 * nn * c * power);
     if (power == 2) {
-      SK_LAUNCH((launch_wilson_arnoldi<T, T, T>(op, U, w.W + (size_t)j * n, tmp, adjoint, src, skip, s)));
+      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, tmp, adjoint, nullptr, skip, s)));
       SK_LAUNCH((launch_wilson<T, T, T>(op, U, tmp, wj1, adjoint, nullptr, skip, s)));
     } else {
-      SK_LAUNCH((launch_wilson_arnoldi<T, T, T>(op, U, w.W + (size_t)j * n, wj1, adjoint, src, skip, s)));
+      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, wj1, adjoint, nullptr, skip, s)));
     }
     t.end();
+    // V_j^H [u, z]: j basis vectors + u + z read once
     t.begin(SK_K_GS_DOT, (j + 2) * nn * c);
-    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, true, w.gpart, skip, s)));
+    SK_LAUNCH((dc_dot<T>(w.W, n, j, true, n, w.gpart, skip, s)));
     t.end();
-    t.begin(SK_K_GS_UPD_DOT, (2 * j + 4) * nn * c);
-    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 1, w.gpart, a, w.norm_part, skip, s)));
-    SK_LAUNCH((gs_dot<T>(w.W, n, j + 1, wj1, n, false, w.gpart, skip, s)));
-    t.end();
-    t.begin(SK_K_GS_UPD_NORM, (j + 3) * nn * c);
-    SK_LAUNCH((gs_update<T>(w.W, n, j, wj1, n, 2, w.gpart, a, w.norm_part, skip, s)));
+    // v_j and u_{j+1} from one pass over V_j (+ read u, z; write v_j, u_{j+1})
+    t.begin(SK_K_GS_UPD_DOT, (j + 4) * nn * c);
+    SK_LAUNCH((dc_update<T>(w.W, n, j, false, n, w.gpart, a, sb(j - 1), sb(j), j == j0 && j0 > 0,
+                            skip, s)));
     t.end();
   }
-  SK_LAUNCH(gs_finish(w.norm_part, n, k - 1, a, skip, s));
+  t.begin(SK_K_GS_UPD_NORM, (2 * k + 3) * nn * c);
+  SK_LAUNCH((dc_dot<T>(w.W, n, k, false, n, w.gpart, skip, s)));
+  SK_LAUNCH((dc_update<T>(w.W, n, k, true, n, w.gpart, a, sb(k - 1), sb(k), k == j0 && j0 > 0, skip,
+                          s)));
+  t.end();
   return SK_OK;
 }
 

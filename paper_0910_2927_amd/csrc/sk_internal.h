@@ -120,6 +120,16 @@ hipError_t gs_update(T* W, int64_t ldq, int j, T* w, int64_t n, int pass, const 
 hipError_t gs_finish(const double* norm_part, int64_t n, int j, const ArnoldiDev& arn,
                      const int* skip, hipStream_t s);
 
+// Arnoldi step kernels with delayed reorthogonalisation (dcgs2.hip).
+// Partials need gs_row_blocks(n) x (2 k + 2) entries.
+template <typename T>
+hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
+                  const int* skip, hipStream_t s);
+template <typename T>
+hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const double2* part,
+                     const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
+                     const int* skip, hipStream_t s);
+
 // ------------------------------------------------------------ launchers
 // Stencil: out = alpha * H_W(+-mu) in; alpha = *in_scale (nullable = 1).
 template <typename TI, typename TL, typename TO>
@@ -193,6 +203,7 @@ hipError_t launch_grad(const sk_operator* op, const PoleSet& ps, const double2* 
 
 hipError_t launch_zero_counters(unsigned* counter, int n, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t count, hipStream_t s);
+hipError_t launch_fill_value(double* p, int64_t count, double v, hipStream_t s);
 
 size_t ts_partial_entries(int64_t n, int pmax);
 int ts_blocks(int64_t n);

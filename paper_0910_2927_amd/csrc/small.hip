@@ -23,6 +23,14 @@ __global__ __launch_bounds__(kWaves * 64) void k_fom_small(ArnoldiDev arn, int k
                                                            double2* ucoef, double2* ycoef) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int kk = arn.st->kdone;
+  if (kk < 1) {   // no Krylov vector (zero start): no update
+    if (threadIdx.x == 0) {
+      arn.st->upd_norm = 0.0;
+      arn.st->hnext = 0.0;
+    }
+    for (int i = threadIdx.x; i < poles.n; i += blockDim.x) rho[i] = make_double2(0.0, 0.0);
+    return;
+  }
   const int ld = arn.ldh;
   const double beta = arn.st->beta;
   const double2* H = arn.H;

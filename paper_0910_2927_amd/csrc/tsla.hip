@@ -472,6 +472,17 @@ hipError_t launch_zero_counters(unsigned* counter, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
+__global__ void k_fill_value(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_value(double* p, int64_t count, double v, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_value, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_zero(double* p, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_d, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count);
