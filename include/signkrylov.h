@@ -249,6 +249,36 @@ int sign_apply_backward(const sk_operator* op, const sk_sign_params* p, const do
                         sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Algorithm 1 for nsys independent systems at once (many sources, possibly
+ * on several gauge fields and lattice sizes), stepped in lockstep: every
+ * kernel of a restart cycle is one launch for the whole batch, systems
+ * that share a gauge field (same links pointer, dims, kappa, mu, boundary)
+ * share each link load in the stencil, finished systems drop out, and a
+ * cycle is replayed from a captured HIP graph.  Each system follows the
+ * same iteration as sign_apply with the same parameters (same Arnoldi and
+ * small-solve arithmetic; reductions of ||x|| and L^H v are summed in
+ * another order, so results agree to rounding, not bit for bit).
+ *   ops[z]: operator of system z (host array of nsys)
+ *   b[z], x[z]: device, 12 V_z complex double each (host arrays of pointers);
+ *     sources may be shared, solutions must not overlap anything
+ *   m[z], R[z], L[z], F[z]: deflation of system z as in sk_sign_params
+ *     (m nullable = no deflation; R/L/F nullable where m[z] = 0)
+ *   p: poles, k, max_cycles, tol, precision, mixed_switch and
+ *     project_each_cycle shared by all systems; p->m, R, L, F are ignored;
+ *     X_shift must be NULL.  SK_PREC_MIXED switches the whole batch to the
+ *     complex-float basis once every active system meets the switch rule.
+ *   stats: host, nullable, nsys entries (times is not filled).
+ * Returns SK_OK if every system converged, else the status of a failing
+ * one (every x[z] still holds its iterate).
+ */
+size_t sign_apply_batched_workspace_bytes(int nsys, const sk_operator* ops, const int* m,
+                                          const sk_sign_params* p);
+int sign_apply_batched(int nsys, const sk_operator* ops, const double* const* b, double* const* x,
+                       const int* m, const double* const* R, const double* const* L,
+                       const double* const* F, const sk_sign_params* p, sk_stats* stats, void* ws,
+                       size_t ws_bytes, hipStream_t stream);
+
+/*
  * Deflation data for Algorithm 1: the m "critical" eigenvalues of H_W
  * (Sect. 4 -- the paper takes R_m, L_m, Lambda_m as given inputs).
  * Krylov-Schur (thick-restart Arnoldi) on A^2 for its eigenvalues of

@@ -105,6 +105,14 @@ SIGNATURES = [
     ("sk_dense_schur", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.c_int, C.c_int]),
     ("sk_dense_sign", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("sign_apply_batched_workspace_bytes", C.c_size_t, [C.c_int, C.POINTER(SkOperator),
+                                                        C.POINTER(C.c_int),
+                                                        C.POINTER(SkSignParams)]),
+    ("sign_apply_batched", C.c_int, [C.c_int, C.POINTER(SkOperator), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(C.c_void_p), C.POINTER(SkSignParams),
+                                     C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
     ("sign_apply_backward_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator),
                                                          C.POINTER(SkSignParams)]),
     ("sign_apply_backward", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,

@@ -17,7 +17,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["WilsonOperator", "SignResult", "kl_poles", "wilson_apply", "arnoldi_cycle",
-           "multishift_fom_restart", "deflate_project", "sign_apply", "SkError"]
+           "multishift_fom_restart", "deflate_project", "sign_apply", "BatchedSignSolver", "SkError"]
 
 SkError = L.SkError
 
@@ -302,6 +302,102 @@ class SignSolver:
                           converged=bool(st.converged), breakdown=bool(st.breakdown),
                           update_norms=np.array(self._hu[:nc]), betas=np.array(self._hb[:nc]),
                           leaks=np.array(self._hl[:nc]), X_shift=self.X)
+
+
+class BatchedSignSolver:
+    """sign(H_W) b for many systems in one lockstep solve (sign_apply_batched).
+
+    systems: list of (op, deflation) with deflation None or (R, L, F) as for
+    SignSolver; each system's source is given per call.  Systems whose
+    operators share links, dims, kappa, mu and boundary share the stencil's
+    link loads."""
+
+    def __init__(self, systems, sigma, omega, k, tol=1e-9, max_cycles=500, precision="fp64",
+                 mixed_switch=0.0, project_each_cycle=True, hist_cap=4096):
+        self.lib = L.load()
+        if precision in ("mixed", "mixed_c64_only"):
+            for op, _ in systems:
+                op.ensure_c64()
+            if precision == "mixed_c64_only":
+                mixed_switch = 1.0
+        self.nsys = len(systems)
+        if self.nsys < 1:
+            raise ValueError("need at least one system")
+        self.ops = [op for op, _ in systems]
+        self._sg, self.N = _cplx_host(sigma)
+        self._om, _ = _cplx_host(omega)
+        self._ostructs = (L.SkOperator * self.nsys)(*[op.struct() for op in self.ops])
+        self._m = (C.c_int * self.nsys)()
+        self._R = (C.c_void_p * self.nsys)()
+        self._L = (C.c_void_p * self.nsys)()
+        self._F = (C.c_void_p * self.nsys)()
+        self._keep = []
+        for z, (op, defl) in enumerate(systems):
+            if defl is None:
+                continue
+            R, Lv, F = defl
+            m = int(R.shape[0])
+            _need(R, torch.complex128, m * op.n, "R")
+            _need(Lv, torch.complex128, m * op.n, "L")
+            Fc = F.transpose(0, 1).contiguous()   # column-major
+            _need(Fc, torch.complex128, m * m, "F")
+            self._keep += [R, Lv, Fc]
+            self._m[z] = m
+            self._R[z], self._L[z], self._F[z] = R.data_ptr(), Lv.data_ptr(), Fc.data_ptr()
+        p = L.SkSignParams()
+        p.npoles = self.N
+        p.sigma = C.cast(self._sg, C.POINTER(C.c_double))
+        p.omega = C.cast(self._om, C.POINTER(C.c_double))
+        p.k = int(k)
+        p.max_cycles = int(max_cycles)
+        p.tol = float(tol)
+        p.project_each_cycle = 1 if project_each_cycle else 0
+        p.precision = L.SK_PREC_FP64 if precision == "fp64" else L.SK_PREC_MIXED
+        p.mixed_switch = float(mixed_switch)
+        self.params = p
+        nb = self.lib.sign_apply_batched_workspace_bytes(self.nsys, self._ostructs, self._m,
+                                                         C.byref(p))
+        if nb == 0:
+            raise SkError(L.SK_ERR_ARG, "invalid parameters for sign_apply_batched")
+        self.ws = _workspace(nb, self.ops[0].device)
+        self.hist_cap = hist_cap
+        self._hist = [((C.c_double * hist_cap)(), (C.c_double * hist_cap)(), (C.c_double * hist_cap)())
+                      for _ in range(self.nsys)]
+
+    def __call__(self, bs, xs=None, raise_on_error=True):
+        if len(bs) != self.nsys:
+            raise ValueError(f"expected {self.nsys} sources, got {len(bs)}")
+        for z, b in enumerate(bs):
+            _need(b, torch.complex128, self.ops[z].n, f"b[{z}]")
+        if xs is None:
+            xs = [torch.empty_like(b) for b in bs]
+        for z, x in enumerate(xs):
+            _need(x, torch.complex128, self.ops[z].n, f"x[{z}]")
+        bp = (C.c_void_p * self.nsys)(*[b.data_ptr() for b in bs])
+        xp = (C.c_void_p * self.nsys)(*[x.data_ptr() for x in xs])
+        st = (L.SkStats * self.nsys)()
+        for z in range(self.nsys):
+            hu, hb, hl = self._hist[z]
+            st[z].hist_update = C.cast(hu, C.POINTER(C.c_double))
+            st[z].hist_beta = C.cast(hb, C.POINTER(C.c_double))
+            st[z].hist_leak = C.cast(hl, C.POINTER(C.c_double))
+            st[z].hist_cap = self.hist_cap
+        status = self.lib.sign_apply_batched(self.nsys, self._ostructs, bp, xp, self._m, self._R,
+                                             self._L, self._F, C.byref(self.params), st,
+                                             _ptr(self.ws), self.ws.numel(), _stream())
+        if raise_on_error and status != L.SK_OK:
+            L.check(status)
+        out = []
+        for z in range(self.nsys):
+            nc = min(st[z].cycles, self.hist_cap)
+            hu, hb, hl = self._hist[z]
+            out.append(SignResult(x=xs[z], status=L.SK_OK if st[z].converged else status,
+                                  cycles=st[z].cycles, cycles_c64=st[z].cycles_c64,
+                                  matvecs=st[z].matvecs, converged=bool(st[z].converged),
+                                  breakdown=bool(st[z].breakdown),
+                                  update_norms=np.array(hu[:nc]), betas=np.array(hb[:nc]),
+                                  leaks=np.array(hl[:nc])))
+        return out
 
 
 def sign_apply(op, b, sigma, omega, k, **kw):

@@ -24,270 +24,33 @@
 // coefficients live in two alternating buffers so that no block reads
 // what another block of the same launch writes.  As in the other kernels,
 // every reduction is finished by the next launch in a fixed order.
-#include "sk_internal.h"
+#include "dcgs2_dev.h"
 
 namespace sk {
 
 namespace {
 
-constexpr int NT = kTsThreads;
-constexpr int NW = NT / 64;
-constexpr int VC = 8;
+constexpr int kNT = kTsThreads;
+constexpr int kVC = 8;
 
-__device__ inline double2 z2() { return make_double2(0.0, 0.0); }
-
-__device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, int pr, double2* sums,
-                                   double2* scratch) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int i0 = 0; i0 < pr; i0 += 64) {
-    const int i = i0 + lane;
-    double2 acc = z2();
-    if (i < pr) {
-      int b = wid;
-      for (; b + 7 * NW < nrows; b += 8 * NW) {
-        double2 v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(b + u * NW) * pr + i];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
-      }
-      for (; b < nrows; b += NW) acc = cadd(acc, src[(size_t)b * pr + i]);
-    }
-    scratch[threadIdx.x] = acc;
-    __syncthreads();
-    if (wid == 0 && i < pr) {
-      double2 s = scratch[lane];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) s = cadd(s, scratch[w * 64 + lane]);
-      sums[i] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// Partial sums of t = V_j^H u, p = V_j^H z (chunk of VC vectors) and, in
-// chunk 0, alpha = u^H u and gamma = u^H z.  Layout per row block:
-// [t_0..t_{j-1}, p_0..p_{j-1}, alpha, gamma].
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dc_dot(const T* __restrict__ W, int64_t ldq, int j, int has_z,
-                                               int64_t n, int rpt, double2* __restrict__ part,
-                                               const int* skip) {
+__global__ __launch_bounds__(kNT) void k_dc_dot(const T* __restrict__ W, int64_t ldq, int j, int has_z,
+                                                int64_t n, int rpt, double2* __restrict__ part,
+                                                const int* skip) {
   if (skip && *skip) return;
-  __shared__ double2 red[NW][2 * VC + 2];
-  const int rb = blockIdx.x, ch = blockIdx.y;
-  const int i0 = ch * VC;
-  const int cnt = max(0, min(VC, j - i0));
-  const T* u = W + (int64_t)j * ldq;
-  const T* zv = W + (int64_t)(j + 1) * ldq;
-  double2 at[VC], ap[VC];
-  double2 aa = z2(), ag = z2();
-#pragma unroll
-  for (int q = 0; q < VC; ++q) at[q] = ap[q] = z2();
-  const int64_t base = (int64_t)rb * NT * rpt + threadIdx.x;
-  for (int q = 0; q < rpt; ++q) {
-    const int64_t r = base + (int64_t)q * NT;
-    if (r < n) {
-      const double2 uv = ld(u + r);
-      const double2 zz = has_z ? ld(zv + r) : z2();
-#pragma unroll
-      for (int c = 0; c < VC; ++c)
-        if (c < cnt) {
-          const double2 vv = ld(W + (int64_t)(i0 + c) * ldq + r);
-          at[c] = cadd(at[c], cconjmul(vv, uv));
-          if (has_z) ap[c] = cadd(ap[c], cconjmul(vv, zz));
-        }
-      if (ch == 0) {
-        aa.x += cabs2(uv);
-        if (has_z) ag = cadd(ag, cconjmul(uv, zz));
-      }
-    }
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int c = 0; c < VC; ++c) {
-    at[c].x = wave_sum(at[c].x);
-    at[c].y = wave_sum(at[c].y);
-    ap[c].x = wave_sum(ap[c].x);
-    ap[c].y = wave_sum(ap[c].y);
-  }
-  aa.x = wave_sum(aa.x);
-  ag.x = wave_sum(ag.x);
-  ag.y = wave_sum(ag.y);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < VC; ++c) {
-      red[wid][c] = at[c];
-      red[wid][VC + c] = ap[c];
-    }
-    red[wid][2 * VC] = aa;
-    red[wid][2 * VC + 1] = ag;
-  }
-  __syncthreads();
-  const int pr = 2 * j + 2;
-  double2* dst = part + (size_t)rb * pr;
-  const int t = threadIdx.x;
-  if (t < 2 * VC + 2) {
-    double2 s = red[0][t];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) s = cadd(s, red[w][t]);
-    if (t < VC) {
-      if (t < cnt) dst[i0 + t] = s;
-    } else if (t < 2 * VC) {
-      if (t - VC < cnt) dst[j + i0 + (t - VC)] = s;
-    } else if (ch == 0) {
-      dst[2 * j + (t - 2 * VC)] = s;
-    }
-  }
+  dc_dot_body<T>(W, ldq, j, has_z, n, rpt, part, blockIdx.x, blockIdx.y);
 }
 
-// Second pass of u_j and (unless FINAL) first pass of the next vector.
-// `fresh`: first step after a thick restart of the eigensolver, where the
-// columns before j already hold the restarted Rayleigh quotient (kept as is).
 template <typename T, bool FINAL>
-__global__ __launch_bounds__(NT) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
-                                                  int rpt, const double2* __restrict__ part, int nrb,
-                                                  ArnoldiDev arn, const double2* __restrict__ s_prev,
-                                                  double2* __restrict__ s_cur, int fresh,
-                                                  const int* skip) {
+__global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
+                                                   int rpt, const double2* __restrict__ part, int nrb,
+                                                   ArnoldiDev arn, const double2* __restrict__ s_prev,
+                                                   double2* __restrict__ s_cur, int fresh,
+                                                   const int* skip) {
   if (skip && *skip) return;
-  __shared__ double2 sums[2 * kMaxK + 4];
-  __shared__ double2 scratch[NT];
-  __shared__ double2 ct[kMaxK + 2];   // t
-  __shared__ double2 ce[kMaxK + 2];   // e
-  __shared__ double2 cs[kMaxK + 2];   // s_j
-  __shared__ double red[NW];
-  __shared__ double sc[4];            // beta, d/beta (re, im), flag
-  __shared__ double2 cd;
-  const int pr = 2 * j + 2;
-  reduce_cols(part, nrb, pr, sums, scratch);
-  const int tid = threadIdx.x;
-  // |t|^2 and |s_{j-1}|^2
-  double tt = 0.0, ss = 0.0;
-  for (int i = tid; i < j; i += NT) {
-    ct[i] = sums[i];
-    tt += cabs2(sums[i]);
-    if (!fresh) ss += cabs2(s_prev[i]);
-  }
-  tt = wave_sum(tt);
-  ss = wave_sum(ss);
-  if ((tid & 63) == 0) red[tid >> 6] = tt;
-  __syncthreads();
-  if (tid == 0) {
-    double a = 0.0;
-    for (int w = 0; w < NW; ++w) a += red[w];
-    sc[1] = a;
-  }
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = ss;
-  __syncthreads();
-  if (tid == 0) {
-    double sprev = 0.0;
-    for (int w = 0; w < NW; ++w) sprev += red[w];
-    // ||A v_{j-1}||^2 = alpha + ||s_{j-1}||^2 sets the breakdown scale
-    const double alpha = sums[2 * j].x;
-    const double b2 = alpha - sc[1];
-    const double ref2 = alpha + sprev;
-    const bool bad = !isfinite(b2) || !isfinite(ref2);
-    const bool brk = bad || !(b2 > kBreakdownTol * kBreakdownTol * ref2);
-    sc[0] = brk ? 0.0 : sqrt(b2);
-    sc[3] = brk ? 1.0 : 0.0;
-    if (blockIdx.x == 0) {
-      if (bad) arn.st->nonfinite = 1;
-      if (brk) {
-        arn.st->breakdown = 1;
-        arn.st->kdone = j;
-        if (j > 0 && !fresh) arn.H[(size_t)(j - 1) * arn.ldh + j] = z2();
-      } else {
-        if (j > 0 && !fresh) arn.H[(size_t)(j - 1) * arn.ldh + j] = make_double2(sc[0], 0.0);
-        arn.st->kdone = FINAL ? j : j;   // steps whose columns are final
-        if (j == 0) arn.st->beta = sc[0];
-      }
-    }
-  }
-  __syncthreads();
-  // final column j-1 = s_{j-1} + t (also on breakdown: K_j is invariant)
-  if (blockIdx.x == 0 && !fresh)
-    for (int i = tid; i < j; i += NT) arn.H[(size_t)(j - 1) * arn.ldh + i] = cadd(s_prev[i], ct[i]);
-  if (sc[3] != 0.0) return;
-  const double beta = sc[0], ib = 1.0 / beta;
-  if (!FINAL) {
-    // s_j from the reduced quantities; H_j t uses columns 0..j-2 of H and
-    // the final column j-1 = s_{j-1} + t
-    const double2 gamma = sums[2 * j + 1];
-    double2 tp = z2();
-    for (int i = tid; i < j; i += NT) {
-      // (H_j t)_i over columns l >= i-1 (Hessenberg); the last column is
-      // s_{j-1} + t unless the columns came from a thick restart
-      double2 ht = z2();
-      const int lend = (fresh ? j : j - 1);
-      int l = max(0, i - 1);
-      for (; l + 8 <= lend; l += 8) {
-        double2 hv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = arn.H[(size_t)(l + u) * arn.ldh + i];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) ht = cadd(ht, cmul(hv[u], ct[l + u]));
-      }
-      for (; l < lend; ++l) ht = cadd(ht, cmul(arn.H[(size_t)l * arn.ldh + i], ct[l]));
-      if (!fresh && j > 0) ht = cadd(ht, cmul(cadd(s_prev[i], ct[i]), ct[j - 1]));
-      const double2 si = cscale(csub(sums[j + i], ht), ib);     // (p_i - (H_j t)_i) / beta
-      cs[i] = si;
-      ce[i] = cadd(cscale(ht, ib), si);                         // c_i = (H_j t)_i / beta + s_i
-      tp = cadd(tp, cconjmul(ct[i], sums[j + i]));              // t^H p
-    }
-    tp.x = wave_sum(tp.x);
-    tp.y = wave_sum(tp.y);
-    __shared__ double2 tpr[NW];
-    if ((tid & 63) == 0) tpr[tid >> 6] = tp;
-    __syncthreads();
-    if (tid == 0) {
-      double2 a = z2();
-      for (int w = 0; w < NW; ++w) a = cadd(a, tpr[w]);
-      // v_j^H A v_j = ((gamma - t^H p)/beta - beta t_{j-1}) / beta
-      double2 vav = cscale(csub(gamma, a), ib);
-      if (j > 0) vav = csub(vav, cscale(ct[j - 1], beta));
-      vav = cscale(vav, ib);
-      cs[j] = vav;
-      const double2 d = (j > 0) ? cadd(ct[j - 1], vav) : vav;
-      cd = cscale(d, ib);   // d / beta
-    }
-    __syncthreads();
-    for (int i = tid; i < j; i += NT) ce[i] = csub(ce[i], cmul(cd, ct[i]));   // e = c - (d/beta) t
-    if (blockIdx.x == 0)
-      for (int i = tid; i <= j; i += NT) {
-        s_cur[i] = cs[i];
-        arn.H[(size_t)j * arn.ldh + i] = cs[i];   // provisional until step j+1
-      }
-    __syncthreads();
-  }
-  T* u = W + (int64_t)j * ldq;
-  T* zv = W + (int64_t)(j + 1) * ldq;
-  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (r >= n) return;
-  double2 at = z2(), ae = z2();
-  constexpr int B = 16;   // basis loads in flight per thread
-  int i = 0;
-  for (; i + B <= j; i += B) {
-    double2 v[B];
-#pragma unroll
-    for (int q = 0; q < B; ++q) v[q] = ld(W + (int64_t)(i + q) * ldq + r);
-#pragma unroll
-    for (int q = 0; q < B; ++q) {
-      at = cadd(at, cmul(v[q], ct[i + q]));
-      if (!FINAL) ae = cadd(ae, cmul(v[q], ce[i + q]));
-    }
-  }
-  for (; i < j; ++i) {
-    const double2 v = ld(W + (int64_t)i * ldq + r);
-    at = cadd(at, cmul(v, ct[i]));
-    if (!FINAL) ae = cadd(ae, cmul(v, ce[i]));
-  }
-  const double2 uv = ld(u + r);
-  st(u + r, cscale(csub(uv, at), ib));                          // v_j
-  if (!FINAL) {
-    const double2 zz = ld(zv + r);
-    st(zv + r, csub(csub(cscale(zz, ib), cmul(cd, uv)), ae));   // u_{j+1}
-  }
+  (void)rpt;
+  dc_update_body<T, FINAL>(W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
+                           (int64_t)blockIdx.x * kNT + threadIdx.x, blockIdx.x == 0);
 }
 
 }  // namespace
@@ -295,8 +58,8 @@ __global__ __launch_bounds__(NT) void k_dc_update(T* __restrict__ W, int64_t ldq
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
                   const int* skip, hipStream_t s) {
-  dim3 grid(gs_row_blocks(n), j > 0 ? (j + VC - 1) / VC : 1);
-  hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(NT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
+  dim3 grid(gs_row_blocks(n), j > 0 ? (j + kVC - 1) / kVC : 1);
+  hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
                      part, skip);
   return hipGetLastError();
 }
@@ -306,12 +69,12 @@ hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
                      const int* skip, hipStream_t s) {
   const int nrb = gs_row_blocks(n);                  // rows of partials (the dot kernel's grid)
-  const unsigned nb = (unsigned)((n + NT - 1) / NT);  // one row per thread here
+  const unsigned nb = (unsigned)((n + kNT - 1) / kNT);  // one row per thread here
   if (final_pass)
-    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(NT), 0, s, W, ldq, j, n, 1, part, nrb,
+    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, part, nrb,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else
-    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(NT), 0, s, W, ldq, j, n, 1, part, nrb,
+    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, part, nrb,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   return hipGetLastError();
 }

@@ -46,7 +46,6 @@ struct KrylovWs {
   double2* dc;
   double2* dc2;
   double2* gpart;      // Gram-Schmidt partial dots, gs_row_blocks(n) x (2k+2)
-  double* norm_part;   // partial ||w||^2, gs_row_blocks(n)
   double2* sbuf;       // first-pass coefficients, 2 x (k+2) (alternating)
   size_t gpart_cap;    // entries of gpart
   int sbuf_k;          // k the first-pass buffers were sized for
@@ -58,7 +57,6 @@ template <typename T>
 void carve_gs(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
   w.gpart_cap = (size_t)gs_row_blocks(n) * (2 * k + 2);
   w.gpart = c.template take<double2>(w.gpart_cap);
-  w.norm_part = c.template take<double>(gs_row_blocks(n));
   w.sbuf = c.template take<double2>((size_t)2 * (k + 2));
   w.sbuf_k = k;
 }

@@ -63,62 +63,16 @@ struct TsEpiArgs {
   double* dst_scale;       // EPI_BETA: where 1/beta goes
 };
 
-// Finishes ||w_{j+1}|| of Arnoldi step j from per-block partial squared
-// norms (fixed summation order) and decides h_{j+1,j}, s_{j+1} and lucky
-// breakdown.  Every block that calls it computes the same value; only the
-// `writer` block stores H, the scale and the flags.  Returns s_{j+1}
-// (0 after breakdown).  Works for any block size up to 1024.
-__device__ inline double gs_finish_norm(const double* __restrict__ norm_part, int nrb, int j,
-                                        const ArnoldiDev& arn, bool writer) {
-  __shared__ double sred[1024];
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nrb; b += blockDim.x) acc += norm_part[b];
-  sred[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    double s = 0.0;
-    for (int t = threadIdx.x; t < (int)blockDim.x; t += 64) s += sred[t];
-    s = wave_sum(s);
-    if (threadIdx.x == 0) sred[0] = s;
-  }
-  __syncthreads();
-  const double nrm = sqrt(sred[0]);
-  __syncthreads();
-  const double ref = arn.wnorm[j];
-  const bool bad = !isfinite(nrm) || !isfinite(ref);
-  const bool brk = bad || nrm <= kBreakdownTol * ref;
-  if (writer && threadIdx.x == 0) {
-    const size_t idx = (size_t)j * arn.ldh + j + 1;
-    arn.H[idx] = brk ? make_double2(0.0, 0.0) : make_double2(nrm, 0.0);
-    arn.scale[j + 1] = brk ? 0.0 : 1.0 / nrm;
-    arn.st->kdone = j + 1;
-    if (brk) arn.st->breakdown = 1;
-    if (bad) arn.st->nonfinite = 1;
-  }
-  return brk ? 0.0 : 1.0 / nrm;
+// Row blocking of the Gram-Schmidt dot kernels: rows per thread such that
+// about 96 blocks of kTsThreads threads cover a vector of n rows.
+__host__ __device__ inline int gs_rpt(int64_t n) {
+  int64_t r = (n + (int64_t)kTsThreads * 96 - 1) / ((int64_t)kTsThreads * 96);
+  return (int)(r < 1 ? 1 : (r > 8 ? 8 : r));
 }
-
-// Where the stencil takes the scale of its input: a device scalar, or the
-// partial norms of the previous Arnoldi step (then it also finishes h_{j,j-1}).
-struct ScaleSrc {
-  const double* in_scale;    // nullable
-  const double* norm_part;   // nullable: partial ||W_j||^2 of step jprev
-  int nrb;
-  int jprev;
-  ArnoldiDev arn;
-};
-
-// CGS2 kernels of one Arnoldi step (gs.hip).
-int gs_rpt(int64_t n);
-int gs_row_blocks(int64_t n);
-template <typename T>
-hipError_t gs_dot(const T* W, int64_t ldq, int p, const T* w, int64_t n, bool with_norm,
-                  double2* part, const int* skip, hipStream_t s);
-template <typename T>
-hipError_t gs_update(T* W, int64_t ldq, int j, T* w, int64_t n, int pass, const double2* part,
-                     const ArnoldiDev& arn, double* norm_part, const int* skip, hipStream_t s);
-hipError_t gs_finish(const double* norm_part, int64_t n, int j, const ArnoldiDev& arn,
-                     const int* skip, hipStream_t s);
+__host__ __device__ inline int gs_row_blocks(int64_t n) {
+  const int64_t rb = (int64_t)kTsThreads * gs_rpt(n);
+  return (int)((n + rb - 1) / rb);
+}
 
 // Arnoldi step kernels with delayed reorthogonalisation (dcgs2.hip).
 // Partials need gs_row_blocks(n) x (2 k + 2) entries.
@@ -136,11 +90,6 @@ template <typename TI, typename TL, typename TO>
 hipError_t launch_wilson(const sk_operator* op, const TL* links, const TI* in, TO* out,
                          int adjoint, const double* in_scale, const int* skip_flag,
                          hipStream_t s);
-// Arnoldi form: alpha = s_j finished from the previous step's partial norms.
-template <typename TI, typename TL, typename TO>
-hipError_t launch_wilson_arnoldi(const sk_operator* op, const TL* links, const TI* in, TO* out,
-                                 int adjoint, const ScaleSrc& src, const int* skip_flag,
-                                 hipStream_t s);
 
 // Residual form: out = b - (H_W - sigma) in, in double; `in` of type TI.
 template <typename TI>

@@ -68,3 +68,34 @@ def test_host_side_queries_and_argument_errors():
     assert st == _lib.SK_ERR_ARG and b"npoles" in lib.sk_last_error()
     assert lib.deflate_project_workspace_bytes(0, 100) == 0
     assert lib.multishift_fom_restart_workspace_bytes(20, 16) > 0
+
+
+def test_batched_entry_point_host_errors():
+    """sign_apply_batched validates on the host before any launch."""
+    from paper_0910_2927_amd import _lib
+    lib = _lib.load()
+    ops = (_lib.SkOperator * 2)()
+    for o in ops:
+        o.dims[:] = [4, 4, 4, 4]
+        o.kappa = 0.25
+    sig = (C.c_double * 2)(0.0, 1.0)
+    om = (C.c_double * 2)(0.5, 0.0)
+    p = _lib.SkSignParams()
+    p.npoles, p.k, p.max_cycles, p.tol = 1, 10, 10, 1e-8
+    p.sigma = C.cast(sig, C.POINTER(C.c_double))
+    p.omega = C.cast(om, C.POINTER(C.c_double))
+    assert lib.sign_apply_batched_workspace_bytes(2, ops, None, C.byref(p)) > 0
+    assert lib.sign_apply_batched_workspace_bytes(0, ops, None, C.byref(p)) == 0
+    m = (C.c_int * 2)(0, 999)
+    assert lib.sign_apply_batched_workspace_bytes(2, ops, m, C.byref(p)) == 0
+    bp = (C.c_void_p * 2)(1 << 20, 1 << 21)
+    xp = (C.c_void_p * 2)(1 << 22, 1 << 23)
+    # no links
+    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
+                                C.c_void_p(1 << 30), 1 << 20, None)
+    assert st == _lib.SK_ERR_ARG
+    # per-shift solutions are not offered by the batched solver
+    p.X_shift = 1 << 24
+    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
+                                C.c_void_p(1 << 30), 1 << 20, None)
+    assert st == _lib.SK_ERR_ARG and b"per-shift" in lib.sk_last_error()
