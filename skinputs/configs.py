@@ -57,7 +57,11 @@ CONFIGS = {
                  scales={0.1: 1.864, 0.3: 1.827}),
     # 10^4, 16 poles, k = 60, 40 deflated, complex-float stencil/basis + FP64
     "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-10,
-                 precision="mixed", scales={}),
+                 precision="mixed", scales={0.3: 2.422}),
+    # 6^4, the smallest lattice of the multi-source batch: 16 poles, k = 40,
+    # 10 deflated, complex double reference
+    "c6": Config("c6", (6, 6, 6, 6), 0.5, (0.3,), s=8, k=40, m=10, tol=1e-10,
+                 scales={0.3: 1.524}),
     # backward: 8^4, mu = 0.3, 16 poles, k = 50, no deflation
     "cg": Config("cg", (8, 8, 8, 8), 0.6, (0.3,), s=8, k=50, m=0, tol=1e-10,
                  scales={0.3: 1.917}),

@@ -49,7 +49,15 @@ def run(name, mu, c_override=None):
     lmax = float(np.max(np.abs(spla.eigs(A, k=4, which="LM", return_eigenvectors=False, tol=1e-8))))
     out = {"config": name, "mu": mu, "dims": list(dims), "eps": cfg.eps, "lambda_max": lmax}
     if cfg.m > 0:
-        R, Lv, lam, F, lam_all = deflation.lr_arpack(A, AH, cfg.m, extra=8, return_all=True)
+        for extra in (8, 16, 32):   # widen the ARPACK window until the selection is certified
+            try:
+                R, Lv, lam, F, lam_all = deflation.lr_arpack(A, AH, cfg.m, extra=extra,
+                                                             return_all=True)
+                break
+            except RuntimeError as e:
+                if "window" not in str(e) or extra == 32:
+                    raise
+                print(f"{name}: ARPACK window with {extra} extra too small; widening", flush=True)
         res_r, res_l, bi = deflation.projector_checks(A, R, Lv, lam)
         a = float(np.sort(np.abs(lam_all))[cfg.m])
         order = np.lexsort((np.angle(lam), np.abs(lam)))
