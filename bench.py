@@ -37,11 +37,129 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=2,
                     help="restart cycles of the CPU oracle to time (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the multi-source leg (84 sources on 6^4, 8^4, 10^4)")
+    ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB three times (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE hardware counters) and exit")
+    ap.add_argument("--batched-switch", type=float, default=1e-3,
+                    help="relative update below which the batch switches to complex float")
     return ap.parse_args()
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def batched_leg(args, log_prefix="batched"):
+    """The multi-source workload: 12 spin-colour point sources at site 0 plus
+    16 Z2 noise sources on each of the 6^4, 8^4 and 10^4 gauge fields (84
+    independent systems, mu = 0.3), solved in one lockstep batch in mixed
+    precision, against the same 84 solves one by one in complex double."""
+    import torch
+    import skinputs as si
+    from skinputs.configs import CONFIGS
+    from paper_0910_2927_amd import api
+
+    dev = torch.device("cuda:0")
+    mu = 0.3
+    lattices = []
+    for name in ("c6", "c2", "c3"):
+        cfg = CONFIGS[name]
+        c = cfg.scales.get(mu)
+        if c is None:
+            log(f"{log_prefix}: no pole scale for {name} at mu={mu}; leg skipped")
+            return None
+        U = si.gauge_links(cfg.dims, cfg.eps, si.seed_for(cfg.L, "gauge"))
+        links = torch.from_numpy(si.links_soa_from_canonical(U).reshape(-1)).to(dev)
+        op = api.WilsonOperator(links, cfg.dims, cfg.kappa, mu, cfg.antiperiodic_t,
+                                links64=links.to(torch.complex64))
+        R, Lv, F, lam, est = api.deflation_eigensolve(op, cfg.m, nev_extra=16, tol=1e-12)
+        sig, om = api.kl_poles(cfg.s, c)
+        srcs = [si.point_source(cfg.n, 0, sc // 3, sc % 3) for sc in range(12)]
+        srcs += [si.z2_source(cfg.n, si.seed_for(cfg.L, "z2", i)) for i in range(16)]
+        bd = [torch.from_numpy(si.soa_from_canonical(b, cfg.V)).to(dev) for b in srcs]
+        lattices.append(dict(cfg=cfg, op=op, defl=(R, Lv, F), sig=sig, om=om, b=bd))
+        log(f"{log_prefix}: {name} {cfg.dims[0]}^4 ready (m={cfg.m}, c={c}, "
+            f"eigensolve {est['matvecs']} matvecs)")
+    systems, bs = [], []
+    for lt in lattices:
+        for b in lt["b"]:
+            systems.append({"op": lt["op"], "defl": lt["defl"], "k": lt["cfg"].k,
+                            "sigma": lt["sig"], "omega": lt["om"]})
+            bs.append(b)
+    nsys = len(systems)
+    tol, maxc = 1e-10, 400
+    solver = api.BatchedSignSolver(systems, lattices[0]["sig"], lattices[0]["om"], lattices[0]["cfg"].k,
+                                   tol=tol, max_cycles=maxc, precision="mixed",
+                                   mixed_switch=args.batched_switch)
+    xs = [torch.empty_like(b) for b in bs]
+    solver(bs, xs)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = solver(bs, xs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    log(f"{log_prefix}: {nsys} systems in one batch: {tb:.3f} s "
+        f"(cycles {min(r.cycles for r in res)}..{max(r.cycles for r in res)})")
+    # the same solves one by one in complex double
+    ts, errs, cyc1 = 0.0, [], []
+    z = 0
+    for lt in lattices:
+        R, Lv, F = lt["defl"]
+        single = api.SignSolver(lt["op"], lt["sig"], lt["om"], lt["cfg"].k, tol=tol, max_cycles=maxc,
+                                precision="fp64", R=R, Lv=Lv, F=F)
+        x1 = torch.empty_like(lt["b"][0])
+        single(lt["b"][0], x1)          # warm-up per lattice
+        for b in lt["b"]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r1 = single(b, x1)
+            torch.cuda.synchronize()
+            ts += time.perf_counter() - t0
+            cyc1.append(r1.cycles)
+            errs.append(float(torch.linalg.vector_norm(xs[z] - x1) / torch.linalg.vector_norm(x1)))
+            z += 1
+    log(f"{log_prefix}: one by one in complex double: {ts:.3f} s; max rel diff {max(errs):.2e}")
+    # parity with the oracle: the Gaussian source of each lattice, whose x*
+    # the oracle stored at a sample of components, solved as one batch with
+    # the same settings
+    gerr = []
+    gsys, gbs = [], []
+    for lt in lattices:
+        cfg = lt["cfg"]
+        gsys.append({"op": lt["op"], "defl": lt["defl"], "k": cfg.k, "sigma": lt["sig"], "omega": lt["om"]})
+        gbs.append(torch.from_numpy(si.soa_from_canonical(si.gaussian_source(cfg.n, si.seed_for(cfg.L, "b")),
+                                                          cfg.V)).to(dev))
+    gres = api.BatchedSignSolver(gsys, lattices[0]["sig"], lattices[0]["om"], lattices[0]["cfg"].k, tol=tol,
+                                 max_cycles=maxc, precision="mixed",
+                                 mixed_switch=args.batched_switch)(gbs)
+    for lt, r in zip(lattices, gres):
+        cfg = lt["cfg"]
+        gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_mu{mu:g}.json")
+        g = json.load(open(gpath))
+        xs_ = si.canonical_from_soa(r.x.cpu().numpy(), cfg.V)[np.array(g["sample_index"])]
+        ref = np.array(g["x_re"]) + 1j * np.array(g["x_im"])
+        gerr.append(float(np.linalg.norm(xs_ - ref) / np.linalg.norm(ref)))
+    log(f"{log_prefix}: Gaussian sources vs oracle x* samples: " + ", ".join(f"{e:.1e}" for e in gerr))
+    per_lat = []
+    for i, lt in enumerate(lattices):
+        per_lat.append(max(errs[28 * i:28 * (i + 1)]))
+    return {"workload": "12 point (site 0, every spin-colour) + 16 Z2 sources on each of the "
+                        "6^4 (eps 0.5, m 10, k 40), 8^4 (eps 0.6, m 20, k 50) and 10^4 "
+                        f"(eps 0.7, m 40, k 60) fields, mu={mu}, 16 poles at each lattice's "
+                        f"scale, tol={tol}",
+            "systems": nsys, "batched_mixed_solves_per_s": nsys / tb,
+            "single_fp64_solves_per_s": nsys / ts, "ratio": ts / tb,
+            "batched_seconds": tb, "single_seconds": ts,
+            "mixed_switch": args.batched_switch,
+            "cycles_batched": [r.cycles for r in res], "cycles_c64": [r.cycles_c64 for r in res],
+            "cycles_single": cyc1,
+            "max_rel_diff_vs_fp64": max(errs), "max_rel_diff_vs_fp64_per_lattice": per_lat,
+            "sampled_rel_err_vs_oracle_per_lattice": gerr,
+            "all_converged": all(r.converged for r in res),
+            "tile": solver.tile}
 
 
 def main():
@@ -58,6 +176,18 @@ def main():
     from skinputs.configs import CONFIGS
     from paper_0910_2927_amd import api, _lib
 
+    if args.copy_calibration:
+        nbytes = 512 << 20
+        src = torch.ones(nbytes // 16, dtype=torch.complex128, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes, "launches": 3}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": batched_leg(args)}), flush=True)
+        return
     cfg = CONFIGS[args.config]
     mu = args.mu
     precision_run = args.precision or cfg.precision
@@ -169,6 +299,8 @@ def main():
                          f"{tc:.2f} s/cycle, scaled by the {cycles[-1]} cycles a solve takes"}
         log(f"cpu oracle: {tc:.2f} s per cycle on {cores} cores")
 
+    batched = None if args.no_batched else batched_leg(args)
+
     out = {
         "metric": "sign(H_W)b solves/s at 10^4, mu=0.3, rel err 1e-8; stencil HBM GB/s",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
@@ -189,6 +321,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "kernels": kern,
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

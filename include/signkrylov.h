@@ -252,31 +252,55 @@ int sign_apply_backward(const sk_operator* op, const sk_sign_params* p, const do
  * Algorithm 1 for nsys independent systems at once (many sources, possibly
  * on several gauge fields and lattice sizes), stepped in lockstep: every
  * kernel of a restart cycle is one launch for the whole batch, systems
- * that share a gauge field (same links pointer, dims, kappa, mu, boundary)
+ * that share a gauge field (same links pointers, dims, kappa, mu, boundary)
  * share each link load in the stencil, finished systems drop out, and a
  * cycle is replayed from a captured HIP graph.  Each system follows the
  * same iteration as sign_apply with the same parameters (same Arnoldi and
- * small-solve arithmetic; reductions of ||x|| and L^H v are summed in
+ * small-solve arithmetic; the reductions of ||x|| and L^H v are summed in
  * another order, so results agree to rounding, not bit for bit).
- *   ops[z]: operator of system z (host array of nsys)
- *   b[z], x[z]: device, 12 V_z complex double each (host arrays of pointers);
- *     sources may be shared, solutions must not overlap anything
- *   m[z], R[z], L[z], F[z]: deflation of system z as in sk_sign_params
- *     (m nullable = no deflation; R/L/F nullable where m[z] = 0)
- *   p: poles, k, max_cycles, tol, precision, mixed_switch and
- *     project_each_cycle shared by all systems; p->m, R, L, F are ignored;
- *     X_shift must be NULL.  SK_PREC_MIXED switches the whole batch to the
- *     complex-float basis once every active system meets the switch rule.
- *   stats: host, nullable, nsys entries (times is not filled).
- * Returns SK_OK if every system converged, else the status of a failing
- * one (every x[z] still holds its iterate).
  */
-size_t sign_apply_batched_workspace_bytes(int nsys, const sk_operator* ops, const int* m,
+typedef struct {
+  sk_operator op;           /* this system's operator (by value) */
+  const double* b;          /* device, 12 V complex double; may be shared */
+  double* x;                /* device, 12 V complex double; overlaps nothing */
+  int32_t k;                /* restart length (0: p->k) */
+  int32_t m;                /* deflation dimension (0: none) */
+  const double* R;          /* device, as in sk_sign_params (m > 0) */
+  const double* L;
+  const double* F;
+  const double* sigma;      /* host, npoles complex, nullable: p->sigma (each
+                               lattice may need its own pole scale c) */
+  const double* omega;      /* host, nullable: p->omega */
+} sk_batch_system;
+
+/*
+ * p: npoles, max_cycles, tol, precision, mixed_switch, project_each_cycle
+ *   and the default k, sigma, omega shared by all systems; p->m, R, L, F
+ *   are ignored; X_shift must be NULL.  SK_PREC_MIXED switches the whole
+ *   batch to the complex-float basis once every active system meets the
+ *   switch rule.
+ * stats: host, nullable, nsys entries (times is not filled).
+ * Returns SK_OK if every system converged, else the status of a failing
+ * one (every x still holds its iterate; stats[z].converged says which).
+ * Workspace: sign_apply_batched_workspace_bytes (0 = invalid arguments).
+ */
+size_t sign_apply_batched_workspace_bytes(int nsys, const sk_batch_system* sys,
                                           const sk_sign_params* p);
-int sign_apply_batched(int nsys, const sk_operator* ops, const double* const* b, double* const* x,
-                       const int* m, const double* const* R, const double* const* L,
-                       const double* const* F, const sk_sign_params* p, sk_stats* stats, void* ws,
-                       size_t ws_bytes, hipStream_t stream);
+int sign_apply_batched(int nsys, const sk_batch_system* sys, const sk_sign_params* p,
+                       sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Row blocking the batched solver's tuner chose for the calling thread's
+ * last sign_apply_batched call: rows per thread of the Gram-Schmidt dot
+ * kernel and of the update kernel.  The tuner times every candidate on the
+ * first call for a batch shape (number and sizes of the systems, k,
+ * precision) and caches the fastest for the life of the process.
+ * Host only; returns SK_ERR_ARG for NULL pointers.
+ */
+int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update);
+/* Fix the row blocking of later batched calls (process-wide; 1..8 rows per
+ * thread each), or hand it back to the tuner with (0, 0).  Host only. */
+int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update);
 
 /*
  * Deflation data for Algorithm 1: the m "critical" eigenvalues of H_W

@@ -63,6 +63,12 @@ class SkStats(C.Structure):
                 ("hist_cap", C.c_int32), ("times", C.POINTER(SkKernelTimes))]
 
 
+class SkBatchSystem(C.Structure):
+    _fields_ = [("op", SkOperator), ("b", C.c_void_p), ("x", C.c_void_p), ("k", C.c_int32),
+                ("m", C.c_int32), ("R", C.c_void_p), ("L", C.c_void_p), ("F", C.c_void_p),
+                ("sigma", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double))]
+
+
 class SkEigParams(C.Structure):
     _fields_ = [("m", C.c_int32), ("nev_extra", C.c_int32), ("ncv", C.c_int32), ("key", C.c_int32),
                 ("tol", C.c_double), ("max_restarts", C.c_int32)]
@@ -105,14 +111,12 @@ SIGNATURES = [
     ("sk_dense_schur", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.c_int, C.c_int]),
     ("sk_dense_sign", C.c_int, [C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
-    ("sign_apply_batched_workspace_bytes", C.c_size_t, [C.c_int, C.POINTER(SkOperator),
-                                                        C.POINTER(C.c_int),
+    ("sign_apply_batched_workspace_bytes", C.c_size_t, [C.c_int, C.POINTER(SkBatchSystem),
                                                         C.POINTER(SkSignParams)]),
-    ("sign_apply_batched", C.c_int, [C.c_int, C.POINTER(SkOperator), C.POINTER(C.c_void_p),
-                                     C.POINTER(C.c_void_p), C.POINTER(C.c_int),
-                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
-                                     C.POINTER(C.c_void_p), C.POINTER(SkSignParams),
+    ("sign_apply_batched", C.c_int, [C.c_int, C.POINTER(SkBatchSystem), C.POINTER(SkSignParams),
                                      C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("sk_batched_last_tile", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("sk_batched_set_tile", C.c_int, [C.c_int, C.c_int]),
     ("sign_apply_backward_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator),
                                                          C.POINTER(SkSignParams)]),
     ("sign_apply_backward", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,

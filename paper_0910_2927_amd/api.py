@@ -308,42 +308,66 @@ class BatchedSignSolver:
     """sign(H_W) b for many systems in one lockstep solve (sign_apply_batched).
 
     systems: list of (op, deflation) with deflation None or (R, L, F) as for
-    SignSolver; each system's source is given per call.  Systems whose
-    operators share links, dims, kappa, mu and boundary share the stencil's
-    link loads."""
+    SignSolver, or of dicts {"op", "defl", "k", "sigma", "omega"} where the
+    last three (optional) override the shared restart length and poles for
+    that system.  sigma, omega: the shared pole set (1-D), or one row per
+    system (2-D, nsys x N).  Each call takes one source per system.  Systems
+    whose operators share links, dims, kappa, mu and boundary share the
+    stencil's link loads."""
 
     def __init__(self, systems, sigma, omega, k, tol=1e-9, max_cycles=500, precision="fp64",
                  mixed_switch=0.0, project_each_cycle=True, hist_cap=4096):
         self.lib = L.load()
-        if precision in ("mixed", "mixed_c64_only"):
-            for op, _ in systems:
-                op.ensure_c64()
-            if precision == "mixed_c64_only":
-                mixed_switch = 1.0
-        self.nsys = len(systems)
+        entries = [s_ if isinstance(s_, dict) else {"op": s_[0], "defl": s_[1]} for s_ in systems]
+        self.nsys = len(entries)
         if self.nsys < 1:
             raise ValueError("need at least one system")
-        self.ops = [op for op, _ in systems]
-        self._sg, self.N = _cplx_host(sigma)
-        self._om, _ = _cplx_host(omega)
-        self._ostructs = (L.SkOperator * self.nsys)(*[op.struct() for op in self.ops])
-        self._m = (C.c_int * self.nsys)()
-        self._R = (C.c_void_p * self.nsys)()
-        self._L = (C.c_void_p * self.nsys)()
-        self._F = (C.c_void_p * self.nsys)()
+        if precision in ("mixed", "mixed_c64_only"):
+            for e in entries:
+                e["op"].ensure_c64()
+            if precision == "mixed_c64_only":
+                mixed_switch = 1.0
+        self.ops = [e["op"] for e in entries]
+        sg = np.asarray(sigma, dtype=np.complex128)
+        og = np.asarray(omega, dtype=np.complex128)
+        if sg.shape != og.shape or sg.ndim not in (1, 2):
+            raise ValueError("sigma and omega must have the same 1-D or 2-D shape")
+        self.N = sg.shape[-1]
+        if sg.ndim == 2:
+            if sg.shape[0] != self.nsys:
+                raise ValueError(f"need one pole row per system ({self.nsys}), got {sg.shape[0]}")
+            for z, e in enumerate(entries):
+                e.setdefault("sigma", sg[z])
+                e.setdefault("omega", og[z])
+            sg, og = sg[0], og[0]
+        self._sg, _ = _cplx_host(sg)
+        self._om, _ = _cplx_host(og)
         self._keep = []
-        for z, (op, defl) in enumerate(systems):
-            if defl is None:
-                continue
-            R, Lv, F = defl
-            m = int(R.shape[0])
-            _need(R, torch.complex128, m * op.n, "R")
-            _need(Lv, torch.complex128, m * op.n, "L")
-            Fc = F.transpose(0, 1).contiguous()   # column-major
-            _need(Fc, torch.complex128, m * m, "F")
-            self._keep += [R, Lv, Fc]
-            self._m[z] = m
-            self._R[z], self._L[z], self._F[z] = R.data_ptr(), Lv.data_ptr(), Fc.data_ptr()
+        self._desc = (L.SkBatchSystem * self.nsys)()
+        for z, e in enumerate(entries):
+            d = self._desc[z]
+            d.op = e["op"].struct()
+            d.k = int(e.get("k") or 0)
+            if e.get("sigma") is not None:
+                ps, n_ = _cplx_host(e["sigma"])
+                po, n2 = _cplx_host(e["omega"])
+                if n_ != self.N or n2 != self.N:
+                    raise ValueError(f"system {z}: expected {self.N} poles")
+                self._keep += [ps, po]
+                d.sigma = C.cast(ps, C.POINTER(C.c_double))
+                d.omega = C.cast(po, C.POINTER(C.c_double))
+            defl = e.get("defl")
+            if defl is not None:
+                R, Lv, F = defl
+                m = int(R.shape[0])
+                op = e["op"]
+                _need(R, torch.complex128, m * op.n, "R")
+                _need(Lv, torch.complex128, m * op.n, "L")
+                Fc = F.transpose(0, 1).contiguous()   # column-major
+                _need(Fc, torch.complex128, m * m, "F")
+                self._keep += [R, Lv, Fc]
+                d.m = m
+                d.R, d.L, d.F = R.data_ptr(), Lv.data_ptr(), Fc.data_ptr()
         p = L.SkSignParams()
         p.npoles = self.N
         p.sigma = C.cast(self._sg, C.POINTER(C.c_double))
@@ -355,14 +379,14 @@ class BatchedSignSolver:
         p.precision = L.SK_PREC_FP64 if precision == "fp64" else L.SK_PREC_MIXED
         p.mixed_switch = float(mixed_switch)
         self.params = p
-        nb = self.lib.sign_apply_batched_workspace_bytes(self.nsys, self._ostructs, self._m,
-                                                         C.byref(p))
+        nb = self.lib.sign_apply_batched_workspace_bytes(self.nsys, self._desc, C.byref(p))
         if nb == 0:
             raise SkError(L.SK_ERR_ARG, "invalid parameters for sign_apply_batched")
         self.ws = _workspace(nb, self.ops[0].device)
         self.hist_cap = hist_cap
         self._hist = [((C.c_double * hist_cap)(), (C.c_double * hist_cap)(), (C.c_double * hist_cap)())
                       for _ in range(self.nsys)]
+        self.tile = None
 
     def __call__(self, bs, xs=None, raise_on_error=True):
         if len(bs) != self.nsys:
@@ -373,8 +397,8 @@ class BatchedSignSolver:
             xs = [torch.empty_like(b) for b in bs]
         for z, x in enumerate(xs):
             _need(x, torch.complex128, self.ops[z].n, f"x[{z}]")
-        bp = (C.c_void_p * self.nsys)(*[b.data_ptr() for b in bs])
-        xp = (C.c_void_p * self.nsys)(*[x.data_ptr() for x in xs])
+            self._desc[z].b = bs[z].data_ptr()
+            self._desc[z].x = x.data_ptr()
         st = (L.SkStats * self.nsys)()
         for z in range(self.nsys):
             hu, hb, hl = self._hist[z]
@@ -382,11 +406,13 @@ class BatchedSignSolver:
             st[z].hist_beta = C.cast(hb, C.POINTER(C.c_double))
             st[z].hist_leak = C.cast(hl, C.POINTER(C.c_double))
             st[z].hist_cap = self.hist_cap
-        status = self.lib.sign_apply_batched(self.nsys, self._ostructs, bp, xp, self._m, self._R,
-                                             self._L, self._F, C.byref(self.params), st,
+        status = self.lib.sign_apply_batched(self.nsys, self._desc, C.byref(self.params), st,
                                              _ptr(self.ws), self.ws.numel(), _stream())
         if raise_on_error and status != L.SK_OK:
             L.check(status)
+        a, b_ = C.c_int(), C.c_int()
+        self.lib.sk_batched_last_tile(C.byref(a), C.byref(b_))
+        self.tile = {"dot_rows_per_thread": a.value, "update_rows_per_thread": b_.value}
         out = []
         for z in range(self.nsys):
             nc = min(st[z].cycles, self.hist_cap)

@@ -12,6 +12,8 @@
 #include "dcgs2_dev.h"
 #include "small_dev.h"
 
+#include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -23,20 +25,24 @@ constexpr int kBNT = kTsThreads;
 constexpr int kMaxGroupRhs = 64;
 constexpr int kSites = 64;            // sites per stencil block
 constexpr int kBStencilThreads = 512; // one wave per hop
+constexpr int kRhsPerBlock = 4;       // right-hand sides per stencil block (links held across them)
 
 // One system of the batch.
 struct BSys {
   int64_t n;
+  int k;               // this system's restart length
   int group;
   double2* W64;        // complex-double basis, (k+1) x n
   float2* W32;         // complex-float basis (mixed precision), or null
   ArnoldiDev arn;      // H (ld k+1), scale (ones), st
-  double2* gpart;      // Gram-Schmidt partial dots, gs_row_blocks(n) x (2k+2)
+  double2* gpart;      // Gram-Schmidt partial dots, row blocks x (2k+2)
   double2* sbuf;       // first-pass coefficients, 2 x (k+2)
   double2* rho;        // N
   double2* Y;          // N x k
   double2* U;          // N x k x k
   double2* ucoef;      // k + 1
+  const double2* sigma;   // this system's poles and weights (npoles each)
+  const double2* omega;
   double2* x;          // solution (caller)
   const double2* b;    // source (caller)
   double* xpart;       // partial ||x||^2 per row block of kBNT rows
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(kBStencilThreads) void k_bstencil(const BGroup* __r
   const StencilGeom& g = G.g;
   const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
   const int s = blockIdx.x * kSites + lane;
-  if (blockIdx.x * kSites >= g.V) return;
+  if (blockIdx.x * kSites >= g.V || (int)blockIdx.y * kRhsPerBlock >= G.nsys) return;
   const bool act_site = s < g.V;
   __shared__ double2 hs[8][6][64];
   // neighbour, hop factor and this wave's link, once for all right-hand sides
@@ -123,10 +129,11 @@ __global__ __launch_bounds__(kBStencilThreads) void k_bstencil(const BGroup* __r
       default: load_hop_link<7>(u, U, g.V, ulink); break;
     }
   }
-  for (int rr = 0; rr < G.nsys; ++rr) {
+  const int rend = min(G.nsys, (int)(blockIdx.y + 1) * kRhsPerBlock);
+  for (int rr = blockIdx.y * kRhsPerBlock; rr < rend; ++rr) {
     const int z = G.sys[rr];
     const BSys& S = sys[z];
-    if (!live(S, act, z)) continue;   // uniform over the block
+    if (j >= S.k || !live(S, act, z)) continue;   // uniform over the block
     const T* in = basis<T>(S) + (int64_t)j * S.n;
     T* out = basis<T>(S) + (int64_t)(j + 1) * S.n;
     if (act_site) {
@@ -168,35 +175,88 @@ __global__ __launch_bounds__(kBStencilThreads) void k_bstencil(const BGroup* __r
 }
 
 // ---- Gram-Schmidt (delayed reorthogonalisation) for every live system
-template <typename T>
-__global__ __launch_bounds__(kBNT) void k_bdot(const BSys* __restrict__ sys, const int* __restrict__ act,
-                                               int j, int has_z) {
-  const int z = blockIdx.z;
-  const BSys& S = sys[z];
-  if (!live(S, act, z)) return;
-  if ((int)blockIdx.x >= gs_row_blocks(S.n)) return;
-  dc_dot_body<T>(basis<T>(S), S.n, j, has_z, S.n, gs_rpt(S.n), S.gpart, blockIdx.x, blockIdx.y);
+// Row blocking of the batched Gram-Schmidt kernels, chosen by the tuner:
+// rpt rows per thread in the dot kernel (hence row blocks of partial sums),
+// urt rows per thread in the update kernel.
+struct BTile {
+  int rpt;
+  int urt;
+};
+__host__ __device__ inline int brow_blocks(int64_t n, int rpt) {
+  const int64_t rb = (int64_t)kBNT * rpt;
+  return (int)((n + rb - 1) / rb);
 }
 
-template <typename T, bool FINAL>
-__global__ __launch_bounds__(kBNT) void k_bupdate(const BSys* __restrict__ sys,
-                                                  const int* __restrict__ act, int j, int k) {
+// Step j of every live system with j <= k (z = A u_j is there for j < k;
+// j = k is the final second pass of the last vector).
+template <typename T>
+__global__ __launch_bounds__(kBNT) void k_bdot(const BSys* __restrict__ sys, const int* __restrict__ act,
+                                               int j, BTile tile) {
   const int z = blockIdx.z;
   const BSys& S = sys[z];
-  if (!live(S, act, z)) return;
-  if ((int64_t)blockIdx.x * kBNT >= S.n) return;
-  dc_update_body<T, FINAL>(basis<T>(S), S.n, j, S.n, S.gpart, gs_row_blocks(S.n), S.arn,
+  if (j > S.k || !live(S, act, z)) return;
+  if ((int)blockIdx.x >= brow_blocks(S.n, tile.rpt)) return;
+  dc_dot_body<T>(basis<T>(S), S.n, j, j < S.k ? 1 : 0, S.n, tile.rpt, S.gpart, blockIdx.x, blockIdx.y);
+}
+
+// Fold the dot partials of systems with many row blocks into kGsGroups rows
+// (stored after them), so that update blocks read a few rows only.
+__global__ __launch_bounds__(kBNT) void k_breduce(const BSys* __restrict__ sys, const int* __restrict__ act,
+                                                  int j, BTile tile) {
+  const int z = blockIdx.z;
+  const BSys& S = sys[z];
+  if (j > S.k || !live(S, act, z)) return;
+  const int nrb = brow_blocks(S.n, tile.rpt);
+  if (!gs_reduced(nrb)) return;
+  const int pr = 2 * j + 2;
+  dc_reduce_body(S.gpart, nrb, pr, S.gpart + (size_t)nrb * pr, blockIdx.x, blockIdx.y);
+}
+
+// FINAL: systems whose k is j; otherwise systems with j < k.
+template <typename T, bool FINAL>
+__global__ __launch_bounds__(kBNT) void k_bupdate(const BSys* __restrict__ sys,
+                                                  const int* __restrict__ act, int j, BTile tile) {
+  const int z = blockIdx.z;
+  const BSys& S = sys[z];
+  if ((FINAL ? j != S.k : j >= S.k) || !live(S, act, z)) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kBNT * tile.urt;
+  if (r0 >= S.n) return;
+  const int k = S.k;
+  const int nrb = brow_blocks(S.n, tile.rpt);
+  const double2* src = gs_reduced(nrb) ? S.gpart + (size_t)nrb * (2 * j + 2) : S.gpart;
+  dc_update_body<T, FINAL>(basis<T>(S), S.n, j, S.n, src, gs_reduced(nrb) ? kGsGroups : nrb, S.arn,
                            S.sbuf + (size_t)((j - 1) & 1) * (k + 2), S.sbuf + (size_t)(j & 1) * (k + 2),
-                           0, (int64_t)blockIdx.x * kBNT + threadIdx.x, blockIdx.x == 0);
+                           0, r0 + threadIdx.x, tile.urt, blockIdx.x == 0);
+}
+
+// Tuning data: slot i (i <= j) is the indicator of rows r = i mod (j + 2)
+// (mutually orthogonal, so the step runs its full course without a
+// breakdown) and slot j + 1 is all ones.  Timing does not depend on values.
+template <typename T>
+__global__ __launch_bounds__(kBNT) void k_btune_fill(const BSys* __restrict__ sys, int j) {
+  const BSys& S = sys[blockIdx.z];
+  const int64_t r = (int64_t)blockIdx.x * kBNT + threadIdx.x;
+  if (r >= S.n) return;
+  T* W = basis<T>(S);
+  const int64_t mod = r % (j + 2);
+  for (int i = 0; i <= j + 1; ++i)
+    st(W + (int64_t)i * S.n + r, make_double2((i == j + 1 || mod == i) ? 1.0 : 0.0, 0.0));
 }
 
 // ---- shifted Hessenberg solves: one workgroup per live system
-__global__ __launch_bounds__(1024) void k_bsmall(const BSys* __restrict__ sys, const int* __restrict__ act,
-                                                 int k, PoleSet poles) {
+__global__ __launch_bounds__(kWaves * 64) void k_bsmall(const BSys* __restrict__ sys,
+                                                         const int* __restrict__ act, int npoles) {
   const int z = blockIdx.x;
   const BSys& S = sys[z];
   if (act[z] == 0) return;
-  fom_small_body(S.arn, k, poles, S.rho, S.Y, S.U, S.ucoef, nullptr);
+  __shared__ PoleSet poles;
+  if (threadIdx.x == 0) poles.n = npoles;
+  for (int i = threadIdx.x; i < npoles; i += blockDim.x) {
+    poles.sigma[i] = S.sigma[i];
+    poles.omega[i] = S.omega[i];
+  }
+  __syncthreads();
+  fom_small_body(S.arn, S.k, poles, S.rho, S.Y, S.U, S.ucoef, nullptr);
 }
 
 // ---- x += V_k u and partial ||x||^2
@@ -257,7 +317,7 @@ __global__ __launch_bounds__(kBNT) void k_bxnorm(const BSys* __restrict__ sys, c
 // ---- deflation: partial L^H v over row blocks (v = basis slot `slot`, or b)
 template <typename T>
 __global__ __launch_bounds__(kBNT) void k_bpdot(const BSys* __restrict__ sys, const int* __restrict__ act,
-                                                int slot, int from_b) {
+                                                int from_b) {
   const int z = blockIdx.z;
   const BSys& S = sys[z];
   if (act[z] == 0 || S.m == 0) return;
@@ -275,7 +335,7 @@ __global__ __launch_bounds__(kBNT) void k_bpdot(const BSys* __restrict__ sys, co
   for (int q = 0; q < rpt; ++q) {
     const int64_t r = base + (int64_t)q * kBNT;
     if (r >= S.n) break;
-    const double2 v = from_b ? S.b[r] : ld(basis<T>(S) + (int64_t)slot * S.n + r);
+    const double2 v = from_b ? S.b[r] : ld(basis<T>(S) + (int64_t)S.k * S.n + r);
 #pragma unroll
     for (int c = 0; c < 8; ++c)
       if (c < cnt) acc[c] = cadd(acc[c], cconjmul(S.L[(int64_t)(i0 + c) * S.n + r], v));
@@ -300,8 +360,8 @@ __global__ __launch_bounds__(kBNT) void k_bpdot(const BSys* __restrict__ sys, co
 // r = v - R (L^H v) into basis slot 0 of precision TN (v = slot k of T, or b);
 // with init: also x = R F (L^H b).  Without deflation: r = v, x = 0 (init).
 template <typename T, typename TN, bool INIT>
-__global__ __launch_bounds__(kBNT) void k_bproject(const BSys* __restrict__ sys, const int* __restrict__ act,
-                                                   int slot) {
+__global__ __launch_bounds__(kBNT) void k_bproject(const BSys* __restrict__ sys,
+                                                   const int* __restrict__ act) {
   const int z = blockIdx.z;
   const BSys& S = sys[z];
   if (act[z] == 0) return;
@@ -329,7 +389,7 @@ __global__ __launch_bounds__(kBNT) void k_bproject(const BSys* __restrict__ sys,
   }
   const int64_t r = (int64_t)blockIdx.x * kBNT + threadIdx.x;
   if (r >= S.n) return;
-  double2 v = INIT ? S.b[r] : ld(basis<T>(S) + (int64_t)slot * S.n + r);
+  double2 v = INIT ? S.b[r] : ld(basis<T>(S) + (int64_t)S.k * S.n + r);
   double2 xp = make_double2(0.0, 0.0);
   for (int i = 0; i < mp; ++i) {
     const double2 Ri = S.R[(int64_t)i * S.n + r];
@@ -340,13 +400,15 @@ __global__ __launch_bounds__(kBNT) void k_bproject(const BSys* __restrict__ sys,
   if (INIT) S.x[r] = xp;
 }
 
-__global__ void k_binit(const BSys* __restrict__ sys, int nsys, int npoles, int k) {
+__global__ void k_binit(const BSys* __restrict__ sys, int nsys, int npoles) {
   const int z = blockIdx.x;
   if (z >= nsys) return;
   const BSys& S = sys[z];
+  const int k = S.k;
   for (int i = threadIdx.x; i < (k + 1) * k; i += blockDim.x) S.arn.H[i] = make_double2(0.0, 0.0);
   for (int i = threadIdx.x; i < k + 2; i += blockDim.x) S.arn.scale[i] = 1.0;
   for (int i = threadIdx.x; i < npoles; i += blockDim.x) S.rho[i] = make_double2(1.0, 0.0);
+  for (int i = threadIdx.x; i < 2 * (k + 2); i += blockDim.x) S.sbuf[i] = make_double2(0.0, 0.0);
   if (threadIdx.x == 0) {
     CycleState* st = S.arn.st;
     st->beta = st->xnorm2 = st->upd_norm = st->leak = st->hnext = 0.0;
@@ -356,28 +418,33 @@ __global__ void k_binit(const BSys* __restrict__ sys, int nsys, int npoles, int 
 
 // ---- host side
 struct BatchPlan {
-  int nsys, ngroups, k, N, mmax;
+  int nsys, ngroups, kmin, kmax, N, mmax;
   int64_t nmax;
+  int maxrb_defl;    // most row blocks of the deflation dots (gs_row_blocks is not monotone in n)
+  int maxrhs;        // most systems in one group
   bool mixed;
+  std::vector<int> kfinal;   // distinct restart lengths (a final pass at each)
   BSys* dsys;        // device descriptors
   BGroup* dgroups;
   int* act;          // device activity mask
   CycleState* st;    // device, nsys contiguous
+  double2* poles;    // device, nsys x (sigma[N], omega[N])
 };
 
-size_t carve_batch(Carver& c, int nsys, const sk_operator* ops, const int* mlist,
-                   const sk_sign_params* p, std::vector<BSys>* hs, int* ngroups_out,
-                   std::vector<BGroup>* hg, BatchPlan* plan) {
-  const int k = p->k, N = p->npoles;
+int sys_k(const sk_batch_system& d, const sk_sign_params* p) { return d.k > 0 ? d.k : p->k; }
+
+size_t carve_batch(Carver& c, int nsys, const sk_batch_system* d, const sk_sign_params* p,
+                   std::vector<BSys>* hs, std::vector<BGroup>* hg, BatchPlan* plan) {
+  const int N = p->npoles;
   const bool mixed = p->precision == SK_PREC_MIXED;
   // groups: systems sharing links, geometry and mu
   std::vector<BGroup> groups;
   std::vector<int> gid(nsys);
   for (int z = 0; z < nsys; ++z) {
-    const sk_operator* o = &ops[z];
+    const sk_operator* o = &d[z].op;
     int found = -1;
     for (size_t q = 0; q < groups.size(); ++q) {
-      const sk_operator* r = &ops[groups[q].sys[0]];
+      const sk_operator* r = &d[groups[q].sys[0]].op;
       if (r->links == o->links && r->links_c64 == o->links_c64 && r->mu == o->mu &&
           r->kappa == o->kappa && r->t_antiperiodic == o->t_antiperiodic &&
           std::memcmp(r->dims, o->dims, sizeof(r->dims)) == 0 && groups[q].nsys < kMaxGroupRhs) {
@@ -398,26 +465,37 @@ size_t carve_batch(Carver& c, int nsys, const sk_operator* ops, const int* mlist
     gid[z] = found;
   }
   if (hg) *hg = groups;
-  if (ngroups_out) *ngroups_out = (int)groups.size();
   BatchPlan pl;
-  std::memset(&pl, 0, sizeof(pl));
+  pl.maxrhs = 1;
+  for (const BGroup& G : groups) pl.maxrhs = std::max(pl.maxrhs, G.nsys);
   pl.nsys = nsys;
   pl.ngroups = (int)groups.size();
-  pl.k = k;
+  pl.kmin = kMaxK;
+  pl.kmax = 0;
   pl.N = N;
+  pl.mmax = 0;
+  pl.nmax = 0;
+  pl.maxrb_defl = 1;
   pl.mixed = mixed;
   pl.dsys = c.take<BSys>(nsys);
   pl.dgroups = c.take<BGroup>(groups.size());
   pl.act = c.take<int>(nsys);
   pl.st = c.take<CycleState>(nsys);
+  pl.poles = c.take<double2>((size_t)nsys * 2 * N);
   if (hs) hs->resize(nsys);
   for (int z = 0; z < nsys; ++z) {
-    const int64_t n = 12 * volume_of(&ops[z]);
+    const int64_t n = 12 * volume_of(&d[z].op);
+    const int k = sys_k(d[z], p);
     pl.nmax = std::max(pl.nmax, n);
-    pl.mmax = std::max(pl.mmax, mlist ? mlist[z] : 0);
+    pl.kmin = std::min(pl.kmin, k);
+    pl.kmax = std::max(pl.kmax, k);
+    if (std::find(pl.kfinal.begin(), pl.kfinal.end(), k) == pl.kfinal.end()) pl.kfinal.push_back(k);
+    pl.mmax = std::max(pl.mmax, d[z].m);
+    pl.maxrb_defl = std::max(pl.maxrb_defl, gs_row_blocks(n));
     BSys S;
     std::memset(&S, 0, sizeof(S));
     S.n = n;
+    S.k = k;
     S.group = gid[z];
     S.W64 = c.take<double2>((size_t)(k + 1) * n);
     S.W32 = mixed ? c.take<float2>((size_t)(k + 1) * n) : nullptr;
@@ -425,14 +503,16 @@ size_t carve_batch(Carver& c, int nsys, const sk_operator* ops, const int* mlist
     S.arn.scale = c.take<double>(k + 2);
     S.arn.ldh = k + 1;
     S.arn.st = pl.st ? pl.st + z : nullptr;
-    S.gpart = c.take<double2>((size_t)gs_row_blocks(n) * (2 * k + 2));
+    S.gpart = c.take<double2>(gs_part_entries(brow_blocks(n, 1), k));   // any tile
     S.sbuf = c.take<double2>((size_t)2 * (k + 2));
     S.rho = c.take<double2>(N);
     S.Y = c.take<double2>((size_t)N * k);
     S.U = c.take<double2>((size_t)N * k * k);
     S.ucoef = c.take<double2>(k + 1);
+    S.sigma = pl.poles ? pl.poles + (size_t)z * 2 * N : nullptr;
+    S.omega = pl.poles ? pl.poles + (size_t)z * 2 * N + N : nullptr;
     S.xpart = c.take<double>((n + kBNT - 1) / kBNT);
-    S.m = mlist ? mlist[z] : 0;
+    S.m = d[z].m;
     S.proj = p->project_each_cycle ? 1 : 0;
     S.dpart = c.take<double2>((size_t)gs_row_blocks(n) * (S.m > 0 ? S.m : 1));
     if (hs) (*hs)[z] = S;
@@ -449,29 +529,67 @@ hipStream_t batch_capture_stream() {
   return cs;
 }
 
-template <typename T, typename TN>
-int enqueue_bcycle(const BatchPlan& P, const PoleSet& ps, hipStream_t s) {
-  const int k = P.k;
-  const int maxtiles = (int)((P.nmax / 12 + kSites - 1) / kSites);
-  const int maxrb = gs_row_blocks(P.nmax);
-  const unsigned maxrows = (unsigned)((P.nmax + kBNT - 1) / kBNT);
-  for (int j = 0; j <= k; ++j) {
-    if (j < k) {
-      hipLaunchKernelGGL((k_bstencil<T>), dim3(maxtiles, 1, P.ngroups), dim3(kBStencilThreads), 0, s,
-                         P.dgroups, P.dsys, P.act, j);
-      SK_LAUNCH(hipGetLastError());
-    }
-    const bool last = (j == k);
-    hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
-                       P.dsys, P.act, j, last ? 0 : 1);
-    SK_LAUNCH(hipGetLastError());
-    if (last)
-      hipLaunchKernelGGL((k_bupdate<T, true>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act, j, k);
-    else
-      hipLaunchKernelGGL((k_bupdate<T, false>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act, j, k);
+// Gram-Schmidt launches of step j: dots, the update of systems still
+// stepping, and the final pass of systems whose restart length is j.
+template <typename T>
+int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
+  const int maxrb = brow_blocks(P.nmax, tile.rpt);
+  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt);
+  hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
+                     P.dsys, P.act, j, tile);
+  SK_LAUNCH(hipGetLastError());
+  if (gs_reduced(maxrb)) {
+    hipLaunchKernelGGL(k_breduce, dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s, P.dsys,
+                       P.act, j, tile);
     SK_LAUNCH(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_bsmall, dim3(P.nsys), dim3(1024), 0, s, P.dsys, P.act, k, ps);
+  if (j < P.kmax) {
+    hipLaunchKernelGGL((k_bupdate<T, false>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act,
+                       j, tile);
+    SK_LAUNCH(hipGetLastError());
+  }
+  if (std::find(P.kfinal.begin(), P.kfinal.end(), j) != P.kfinal.end()) {
+    hipLaunchKernelGGL((k_bupdate<T, true>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act,
+                       j, tile);
+    SK_LAUNCH(hipGetLastError());
+  }
+  return SK_OK;
+}
+
+// One non-final Gram-Schmidt step for the tuner.
+template <typename T>
+int enqueue_bgs_step(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
+  const int maxrb = brow_blocks(P.nmax, tile.rpt);
+  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt);
+  hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
+                     P.dsys, P.act, j, tile);
+  SK_LAUNCH(hipGetLastError());
+  if (gs_reduced(maxrb)) {
+    hipLaunchKernelGGL(k_breduce, dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s, P.dsys,
+                       P.act, j, tile);
+    SK_LAUNCH(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_bupdate<T, false>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act, j,
+                     tile);
+  SK_LAUNCH(hipGetLastError());
+  return SK_OK;
+}
+
+template <typename T, typename TN>
+int enqueue_bcycle(const BatchPlan& P, const BTile& tile, hipStream_t s) {
+  const int maxtiles = (int)((P.nmax / 12 + kSites - 1) / kSites);
+  const int maxrb = P.maxrb_defl;
+  const unsigned maxrows = (unsigned)((P.nmax + kBNT - 1) / kBNT);
+  for (int j = 0; j <= P.kmax; ++j) {
+    if (j < P.kmax) {
+      hipLaunchKernelGGL((k_bstencil<T>), dim3(maxtiles, (P.maxrhs + kRhsPerBlock - 1) / kRhsPerBlock,
+                                               P.ngroups),
+                         dim3(kBStencilThreads), 0, s, P.dgroups, P.dsys, P.act, j);
+      SK_LAUNCH(hipGetLastError());
+    }
+    SK_TRY(enqueue_bgs<T>(P, tile, j, s));
+  }
+  hipLaunchKernelGGL(k_bsmall, dim3(P.nsys), dim3(kWaves * 64), 0, s, P.dsys, P.act, P.N);
   SK_LAUNCH(hipGetLastError());
   hipLaunchKernelGGL((k_bxupdate<T>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act);
   SK_LAUNCH(hipGetLastError());
@@ -479,19 +597,99 @@ int enqueue_bcycle(const BatchPlan& P, const PoleSet& ps, hipStream_t s) {
   SK_LAUNCH(hipGetLastError());
   if (P.mmax > 0) {
     hipLaunchKernelGGL((k_bpdot<T>), dim3(maxrb, (P.mmax + 7) / 8, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                       P.act, k, 0);
+                       P.act, 0);
     SK_LAUNCH(hipGetLastError());
   }
   hipLaunchKernelGGL((k_bproject<T, TN, false>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                     P.act, k);
+                     P.act);
   SK_LAUNCH(hipGetLastError());
   return SK_OK;
 }
 
-int enqueue_bcycle_kind(int kind, const BatchPlan& P, const PoleSet& ps, hipStream_t s) {
-  if (kind == 0) return enqueue_bcycle<double2, double2>(P, ps, s);
-  if (kind == 1) return enqueue_bcycle<double2, float2>(P, ps, s);
-  return enqueue_bcycle<float2, float2>(P, ps, s);
+int enqueue_bcycle_kind(int kind, const BatchPlan& P, const BTile& tile, hipStream_t s) {
+  if (kind == 0) return enqueue_bcycle<double2, double2>(P, tile, s);
+  if (kind == 1) return enqueue_bcycle<double2, float2>(P, tile, s);
+  return enqueue_bcycle<float2, float2>(P, tile, s);
+}
+
+// The tuner: times the Gram-Schmidt step (dots + update, the bulk of a
+// cycle's memory traffic) at j = kmin/2 (every system stepping) for each
+// tile candidate on the batch's own workspace, in the precision most cycles
+// use, and keeps the fastest.  Results are cached per batch shape for the
+// life of the process.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, BTile> g_tune_cache;
+thread_local BTile g_last_tile = {0, 0};
+std::atomic<int> g_force_rpt{0}, g_force_urt{0};   // 0: use the tuner
+
+std::vector<int64_t> tune_key(const BatchPlan& P, const std::vector<BSys>& hs) {
+  std::vector<int64_t> key = {P.mixed ? 1 : 0, P.nsys};
+  for (const BSys& S : hs) {
+    key.push_back(S.n);
+    key.push_back(S.k);
+  }
+  return key;
+}
+
+template <typename T>
+int tune_tiles(const BatchPlan& P, hipStream_t s, BTile* best) {
+  const int j = P.kmin / 2;
+  static const BTile cand[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
+  const dim3 fill_grid((unsigned)brow_blocks(P.nmax, 1), 1, P.nsys);
+  hipEvent_t e0, e1;
+  SK_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return SK_ERR_HIP;
+  }
+  float tbest = 1e30f;
+  int rc = SK_OK;
+  for (const BTile& t : cand) {
+    float tt = 0.0f;
+    for (int rep = 0; rep < 3 && rc == SK_OK; ++rep) {
+      // the update rewrites slots j and j+1, so the data is refilled each time
+      hipLaunchKernelGGL((k_btune_fill<T>), fill_grid, dim3(kBNT), 0, s, P.dsys, j);
+      if (hipGetLastError() != hipSuccess || hipEventRecord(e0, s) != hipSuccess) rc = SK_ERR_HIP;
+      if (rc == SK_OK) {
+        rc = enqueue_bgs_step<T>(P, t, j, s);
+      }
+      if (rc == SK_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = SK_ERR_HIP;
+      float ms = 0.0f;
+      if (rc == SK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = SK_ERR_HIP;
+      if (rep > 0) tt += ms;   // the first repetition warms caches and code
+    }
+    if (rc != SK_OK) break;
+    if (tt < tbest) {
+      tbest = tt;
+      *best = t;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != SK_OK) set_error("tile tuning failed");
+  return rc;
+}
+
+int check_batch(int nsys, const sk_batch_system* d, const sk_sign_params* p, char* msg, size_t len) {
+  if (nsys < 1 || !d || !p) return snprintf(msg, len, "NULL argument or nsys < 1"), 0;
+  if (p->npoles < 1 || p->npoles > kMaxPoles) return snprintf(msg, len, "npoles outside [1, %d]", kMaxPoles), 0;
+  if (p->k < 0 || p->k > kMaxK) return snprintf(msg, len, "k = %d outside [1, %d]", p->k, kMaxK), 0;
+  if (p->max_cycles < 1 || !(p->tol > 0.0)) return snprintf(msg, len, "max_cycles and tol must be positive"), 0;
+  if (p->precision != SK_PREC_FP64 && p->precision != SK_PREC_MIXED) return snprintf(msg, len, "unknown precision"), 0;
+  if (p->X_shift) return snprintf(msg, len, "per-shift solutions are not available in the batched solver"), 0;
+  if (p->mixed_switch < 0.0) return snprintf(msg, len, "mixed_switch must be >= 0"), 0;
+  for (int z = 0; z < nsys; ++z) {
+    if (volume_of(&d[z].op) <= 0) return snprintf(msg, len, "system %d: bad lattice dims", z), 0;
+    const int k = sys_k(d[z], p);
+    if (k < 1 || k > kMaxK || d[z].k < 0)
+      return snprintf(msg, len, "system %d: restart length %d outside [1, %d]", z, k, kMaxK), 0;
+    if (d[z].m < 0 || d[z].m > kMaxDefl) return snprintf(msg, len, "system %d: m = %d outside [0, %d]", z, d[z].m, kMaxDefl), 0;
+    if (!(d[z].sigma || p->sigma) || !(d[z].omega || p->omega))
+      return snprintf(msg, len, "system %d: no poles given", z), 0;
+  }
+  return 1;
 }
 
 }  // namespace
@@ -501,99 +699,136 @@ using namespace sk;
 
 extern "C" {
 
-size_t sign_apply_batched_workspace_bytes(int nsys, const sk_operator* ops, const int* m,
-                                          const sk_sign_params* p) {
-  if (nsys < 1 || !ops || !p || p->k < 1 || p->k > kMaxK || p->npoles < 1 || p->npoles > kMaxPoles)
-    return 0;
-  for (int z = 0; z < nsys; ++z)
-    if (volume_of(&ops[z]) <= 0 || (m && (m[z] < 0 || m[z] > kMaxDefl))) return 0;
+size_t sign_apply_batched_workspace_bytes(int nsys, const sk_batch_system* sys, const sk_sign_params* p) {
+  char msg[256];
+  if (!check_batch(nsys, sys, p, msg, sizeof msg)) return 0;
   Carver c;
-  return carve_batch(c, nsys, ops, m, p, nullptr, nullptr, nullptr, nullptr);
+  return carve_batch(c, nsys, sys, p, nullptr, nullptr, nullptr);
 }
 
-int sign_apply_batched(int nsys, const sk_operator* ops, const double* const* b, double* const* x,
-                       const int* m, const double* const* R, const double* const* L,
-                       const double* const* F, const sk_sign_params* p, sk_stats* stats, void* ws,
-                       size_t ws_bytes, hipStream_t stream) {
-  SK_CHECK(nsys >= 1 && ops && b && x && p && ws, "NULL argument or nsys < 1");
-  SK_CHECK(p->k >= 1 && p->k <= kMaxK, "k = %d outside [1, %d]", p->k, kMaxK);
-  SK_CHECK(p->npoles >= 1 && p->npoles <= kMaxPoles, "npoles outside [1, %d]", kMaxPoles);
-  SK_CHECK(p->max_cycles >= 1 && p->tol > 0.0, "max_cycles and tol must be positive");
-  SK_CHECK(p->precision == SK_PREC_FP64 || p->precision == SK_PREC_MIXED, "unknown precision");
-  SK_CHECK(p->X_shift == nullptr, "per-shift solutions are not available in the batched solver");
-  SK_CHECK(!(p->mixed_switch < 0.0), "mixed_switch must be >= 0");
+int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update) {
+  const bool off = rows_per_thread_dot == 0 && rows_per_thread_update == 0;
+  SK_CHECK(off || (rows_per_thread_dot >= 1 && rows_per_thread_dot <= 8 && rows_per_thread_update >= 1 &&
+                   rows_per_thread_update <= 8),
+           "rows per thread must be 1..8 (or both 0 for the tuner)");
+  g_force_urt.store(rows_per_thread_update);
+  g_force_rpt.store(rows_per_thread_dot);
+  return SK_OK;
+}
+
+int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update) {
+  SK_CHECK(rows_per_thread_dot && rows_per_thread_update, "NULL argument");
+  *rows_per_thread_dot = g_last_tile.rpt;
+  *rows_per_thread_update = g_last_tile.urt;
+  return SK_OK;
+}
+
+int sign_apply_batched(int nsys, const sk_batch_system* d, const sk_sign_params* p, sk_stats* stats,
+                       void* ws, size_t ws_bytes, hipStream_t stream) {
+  char msg[256];
+  SK_CHECK(check_batch(nsys, d, p, msg, sizeof msg), "%s", msg);
+  SK_CHECK(ws != nullptr, "workspace is NULL");
   const bool mixed = p->precision == SK_PREC_MIXED;
   for (int z = 0; z < nsys; ++z) {
-    SK_TRY(check_operator(&ops[z], SK_C128));
-    if (mixed) SK_TRY(check_operator(&ops[z], SK_C64));
-    SK_CHECK(b[z] && x[z], "b[%d] / x[%d] is NULL", z, z);
-    const size_t nb = (size_t)12 * volume_of(&ops[z]) * 16;
-    SK_CHECK(!overlap(b[z], nb, x[z], nb), "system %d: b and x overlap", z);
+    SK_TRY(check_operator(&d[z].op, SK_C128));
+    if (mixed) SK_TRY(check_operator(&d[z].op, SK_C64));
+    SK_CHECK(d[z].b && d[z].x, "system %d: b or x is NULL", z);
+    if (d[z].m > 0) SK_CHECK(d[z].R && d[z].L && d[z].F, "system %d: m > 0 needs R, L, F", z);
+    const size_t nb = (size_t)12 * volume_of(&d[z].op) * 16;
+    SK_CHECK(!overlap(d[z].b, nb, d[z].x, nb), "system %d: b and x overlap", z);
     for (int y = 0; y < z; ++y) {
-      const size_t ny = (size_t)12 * volume_of(&ops[y]) * 16;
-      SK_CHECK(!overlap(x[y], ny, x[z], nb) && !overlap(b[y], ny, x[z], nb) && !overlap(x[y], ny, b[z], nb),
+      const size_t ny = (size_t)12 * volume_of(&d[y].op) * 16;
+      SK_CHECK(!overlap(d[y].x, ny, d[z].x, nb) && !overlap(d[y].b, ny, d[z].x, nb) &&
+                   !overlap(d[y].x, ny, d[z].b, nb),
                "systems %d and %d share solution memory", y, z);
     }
-    const int mz = m ? m[z] : 0;
-    SK_CHECK(mz >= 0 && mz <= kMaxDefl, "m[%d] = %d outside [0, %d]", z, mz, kMaxDefl);
-    if (mz > 0) SK_CHECK(R && L && F && R[z] && L[z] && F[z], "system %d: m > 0 needs R, L, F", z);
   }
-  const size_t need = sign_apply_batched_workspace_bytes(nsys, ops, m, p);
+  const size_t need = sign_apply_batched_workspace_bytes(nsys, d, p);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
     return SK_ERR_WORKSPACE;
   }
   for (int z = 0; z < nsys; ++z) {
-    const size_t nb = (size_t)12 * volume_of(&ops[z]) * 16;
-    SK_CHECK(!overlap(ws, need, x[z], nb) && !overlap(ws, need, b[z], nb),
+    const size_t nb = (size_t)12 * volume_of(&d[z].op) * 16;
+    SK_CHECK(!overlap(ws, need, d[z].x, nb) && !overlap(ws, need, d[z].b, nb),
              "workspace overlaps b or x of system %d", z);
   }
-  PoleSet ps;
-  SK_CHECK(p->sigma && p->omega, "sigma/omega are NULL");
-  ps.n = p->npoles;
-  for (int i = 0; i < ps.n; ++i) {
-    ps.sigma[i] = make_double2(p->sigma[2 * i], p->sigma[2 * i + 1]);
-    ps.omega[i] = make_double2(p->omega[2 * i], p->omega[2 * i + 1]);
+  const int N = p->npoles;
+  // per-system pole table: sigma then omega
+  std::vector<double2> ptab((size_t)nsys * 2 * N);
+  for (int z = 0; z < nsys; ++z) {
+    const double* sg = d[z].sigma ? d[z].sigma : p->sigma;
+    const double* om = d[z].omega ? d[z].omega : p->omega;
+    for (int i = 0; i < N; ++i) {
+      SK_CHECK(std::isfinite(sg[2 * i]) && std::isfinite(sg[2 * i + 1]) && std::isfinite(om[2 * i]) &&
+                   std::isfinite(om[2 * i + 1]),
+               "system %d: pole %d is not finite", z, i);
+      ptab[(size_t)z * 2 * N + i] = make_double2(sg[2 * i], sg[2 * i + 1]);
+      ptab[(size_t)z * 2 * N + N + i] = make_double2(om[2 * i], om[2 * i + 1]);
+    }
   }
   Carver c;
   c.base = (char*)ws;
   std::vector<BSys> hs;
   std::vector<BGroup> hg;
   BatchPlan P;
-  int ng = 0;
-  carve_batch(c, nsys, ops, m, p, &hs, &ng, &hg, &P);
+  carve_batch(c, nsys, d, p, &hs, &hg, &P);
   for (int z = 0; z < nsys; ++z) {
-    hs[z].x = (double2*)x[z];
-    hs[z].b = (const double2*)b[z];
+    hs[z].x = (double2*)d[z].x;
+    hs[z].b = (const double2*)d[z].b;
     if (hs[z].m > 0) {
-      hs[z].R = (const double2*)R[z];
-      hs[z].L = (const double2*)L[z];
-      hs[z].F = (const double2*)F[z];
+      hs[z].R = (const double2*)d[z].R;
+      hs[z].L = (const double2*)d[z].L;
+      hs[z].F = (const double2*)d[z].F;
     }
   }
   hipStream_t s = stream;
   SK_HIP(hipMemcpyAsync(P.dsys, hs.data(), nsys * sizeof(BSys), hipMemcpyHostToDevice, s));
-  SK_HIP(hipMemcpyAsync(P.dgroups, hg.data(), ng * sizeof(BGroup), hipMemcpyHostToDevice, s));
+  SK_HIP(hipMemcpyAsync(P.dgroups, hg.data(), hg.size() * sizeof(BGroup), hipMemcpyHostToDevice, s));
+  SK_HIP(hipMemcpyAsync(P.poles, ptab.data(), ptab.size() * sizeof(double2), hipMemcpyHostToDevice, s));
   std::vector<int> act(nsys, 1);
   SK_HIP(hipMemcpyAsync(P.act, act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
-  hipLaunchKernelGGL(k_binit, dim3(nsys), dim3(256), 0, s, P.dsys, nsys, ps.n, P.k);
+  BTile tile = {gs_rpt(P.nmax), 1};
+  if (g_force_rpt.load() > 0) {
+    tile = {g_force_rpt.load(), g_force_urt.load()};
+  } else {
+    const std::vector<int64_t> key = tune_key(P, hs);
+    bool have = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        tile = it->second;
+        have = true;
+      }
+    }
+    if (!have && P.kmin >= 2) {
+      hipLaunchKernelGGL(k_binit, dim3(nsys), dim3(256), 0, s, P.dsys, nsys, N);
+      SK_LAUNCH(hipGetLastError());
+      SK_TRY(mixed ? tune_tiles<float2>(P, s, &tile) : tune_tiles<double2>(P, s, &tile));
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = tile;
+    }
+  }
+  g_last_tile = tile;
+  hipLaunchKernelGGL(k_binit, dim3(nsys), dim3(256), 0, s, P.dsys, nsys, N);
   SK_LAUNCH(hipGetLastError());
   const double theta = !mixed ? 0.0 : (p->mixed_switch > 0.0 ? p->mixed_switch : 1e-3);
   bool low = mixed && theta >= 1.0;
   // x = x_P, W_0 = (I - P) b
-  const int maxrb = gs_row_blocks(P.nmax);
+  const int maxrb = P.maxrb_defl;
   const unsigned maxrows = (unsigned)((P.nmax + kBNT - 1) / kBNT);
   if (P.mmax > 0) {
     hipLaunchKernelGGL((k_bpdot<double2>), dim3(maxrb, (P.mmax + 7) / 8, nsys), dim3(kBNT), 0, s, P.dsys,
-                       P.act, 0, 1);
+                       P.act, 1);
     SK_LAUNCH(hipGetLastError());
   }
   if (low)
     hipLaunchKernelGGL((k_bproject<double2, float2, true>), dim3(maxrows, 1, nsys), dim3(kBNT), 0, s,
-                       P.dsys, P.act, 0);
+                       P.dsys, P.act);
   else
     hipLaunchKernelGGL((k_bproject<double2, double2, true>), dim3(maxrows, 1, nsys), dim3(kBNT), 0, s,
-                       P.dsys, P.act, 0);
+                       P.dsys, P.act);
   SK_LAUNCH(hipGetLastError());
   std::vector<CycleState> st(nsys);
   std::vector<int> small(nsys, 0), status(nsys, SK_ERR_NOCONV);
@@ -614,6 +849,9 @@ int sign_apply_batched(int nsys, const sk_operator* ops, const double* const* b,
   } guard{exec};
   int nact = nsys;
   for (int cyc = 0; cyc < p->max_cycles && nact > 0; ++cyc) {
+    // the whole batch switches to complex float once every active system
+    // meets the switch rule (the next cycle's precision is fixed before this
+    // one is enqueued; once low, it stays low)
     bool all_small = true;
     for (int z = 0; z < nsys; ++z)
       if (act[z] && !(cyc > 0 && st[z].upd_norm <= theta * std::sqrt(st[z].xnorm2))) all_small = false;
@@ -623,7 +861,7 @@ int sign_apply_batched(int nsys, const sk_operator* ops, const double* const* b,
       hipStream_t cs = batch_capture_stream();
       SK_CHECK(cs != nullptr, "could not create the capture stream");
       SK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      const int rc = enqueue_bcycle_kind(kind, P, ps, cs);
+      const int rc = enqueue_bcycle_kind(kind, P, tile, cs);
       hipGraph_t graph = nullptr;
       const hipError_t e = hipStreamEndCapture(cs, &graph);
       if (rc != SK_OK) {

@@ -41,6 +41,12 @@ __global__ __launch_bounds__(kNT) void k_dc_dot(const T* __restrict__ W, int64_t
   dc_dot_body<T>(W, ldq, j, has_z, n, rpt, part, blockIdx.x, blockIdx.y);
 }
 
+__global__ __launch_bounds__(kNT) void k_dc_reduce(const double2* __restrict__ part, int nrb, int pr,
+                                                   double2* __restrict__ out, const int* skip) {
+  if (skip && *skip) return;
+  dc_reduce_body(part, nrb, pr, out, blockIdx.x, blockIdx.y);
+}
+
 template <typename T, bool FINAL>
 __global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
                                                    int rpt, const double2* __restrict__ part, int nrb,
@@ -50,17 +56,25 @@ __global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ld
   if (skip && *skip) return;
   (void)rpt;
   dc_update_body<T, FINAL>(W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
-                           (int64_t)blockIdx.x * kNT + threadIdx.x, blockIdx.x == 0);
+                           (int64_t)blockIdx.x * kNT + threadIdx.x, 1, blockIdx.x == 0);
 }
 
 }  // namespace
 
+// Dots of step j; beyond kGsDirect row blocks the partials are folded into
+// kGsGroups rows stored right after them (part + nrb * (2 j + 2)).
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
                   const int* skip, hipStream_t s) {
-  dim3 grid(gs_row_blocks(n), j > 0 ? (j + kVC - 1) / kVC : 1);
+  const int nrb = gs_row_blocks(n);
+  dim3 grid(nrb, j > 0 ? (j + kVC - 1) / kVC : 1);
   hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
                      part, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !gs_reduced(nrb)) return e;
+  const int pr = 2 * j + 2;
+  hipLaunchKernelGGL(k_dc_reduce, dim3((pr + 63) / 64, kGsGroups), dim3(kNT), 0, s, part, nrb, pr,
+                     part + (size_t)nrb * pr, skip);
   return hipGetLastError();
 }
 
@@ -69,12 +83,15 @@ hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
                      const int* skip, hipStream_t s) {
   const int nrb = gs_row_blocks(n);                  // rows of partials (the dot kernel's grid)
+  const int pr = 2 * j + 2;
+  const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
+  const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
   const unsigned nb = (unsigned)((n + kNT - 1) / kNT);  // one row per thread here
   if (final_pass)
-    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, part, nrb,
+    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else
-    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, part, nrb,
+    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   return hipGetLastError();
 }

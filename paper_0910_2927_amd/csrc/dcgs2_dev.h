@@ -43,6 +43,45 @@ __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, i
   }
 }
 
+// Rows of one dot block: every load of a row is issued before any of it is
+// used (raw values, converted afterwards), so a wave has VC + 2 loads in
+// flight.  FULL: the chunk holds VC vectors (no masking); otherwise
+// vectors past cnt re-read a valid vector and are masked out.
+template <typename T, bool HAS_Z, bool FULL>
+__device__ inline void dot_rows(const T* __restrict__ W, int64_t ldq, int j, int i0, int cnt, int64_t n,
+                                int rpt, int64_t base, bool first, double2 (&at)[VC], double2 (&ap)[VC],
+                                double2& aa, double2& ag) {
+  const T* u = W + (int64_t)j * ldq;
+  const T* zv = u + ldq;
+  const int last = cnt > 0 ? cnt - 1 : 0;
+  const T* vb[VC];
+#pragma unroll
+  for (int c = 0; c < VC; ++c) vb[c] = W + (int64_t)(i0 + (FULL ? c : min(c, last))) * ldq;
+  for (int q = 0; q < rpt; ++q) {
+    const int64_t r = base + (int64_t)q * NT;
+    if (r >= n) break;
+    T raw[VC];
+    const T ru = u[r];
+    T rz;
+    if (HAS_Z) rz = zv[r];
+#pragma unroll
+    for (int c = 0; c < VC; ++c) raw[c] = vb[c][r];
+    const double2 uv = cvt(ru);
+    const double2 zz = HAS_Z ? cvt(rz) : z2();
+#pragma unroll
+    for (int c = 0; c < VC; ++c)
+      if (FULL || c < cnt) {
+        const double2 vv = cvt(raw[c]);
+        at[c] = cadd(at[c], cconjmul(vv, uv));
+        if (HAS_Z) ap[c] = cadd(ap[c], cconjmul(vv, zz));
+      }
+    if (first) {
+      aa.x += cabs2(uv);
+      if (HAS_Z) ag = cadd(ag, cconjmul(uv, zz));
+    }
+  }
+}
+
 // Partial sums of t = V_j^H u, p = V_j^H z (chunk of VC vectors) and, in
 // chunk 0, alpha = u^H u and gamma = u^H z.  Layout per row block:
 // [t_0..t_{j-1}, p_0..p_{j-1}, alpha, gamma].
@@ -52,30 +91,18 @@ __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, 
   __shared__ double2 red[NW][2 * VC + 2];
   const int i0 = ch * VC;
   const int cnt = max(0, min(VC, j - i0));
-  const T* u = W + (int64_t)j * ldq;
-  const T* zv = W + (int64_t)(j + 1) * ldq;
   double2 at[VC], ap[VC];
   double2 aa = z2(), ag = z2();
 #pragma unroll
   for (int q = 0; q < VC; ++q) at[q] = ap[q] = z2();
   const int64_t base = (int64_t)rb * NT * rpt + threadIdx.x;
-  for (int q = 0; q < rpt; ++q) {
-    const int64_t r = base + (int64_t)q * NT;
-    if (r < n) {
-      const double2 uv = ld(u + r);
-      const double2 zz = has_z ? ld(zv + r) : z2();
-#pragma unroll
-      for (int c = 0; c < VC; ++c)
-        if (c < cnt) {
-          const double2 vv = ld(W + (int64_t)(i0 + c) * ldq + r);
-          at[c] = cadd(at[c], cconjmul(vv, uv));
-          if (has_z) ap[c] = cadd(ap[c], cconjmul(vv, zz));
-        }
-      if (ch == 0) {
-        aa.x += cabs2(uv);
-        if (has_z) ag = cadd(ag, cconjmul(uv, zz));
-      }
-    }
+  const bool first = ch == 0;
+  if (has_z) {
+    if (cnt == VC) dot_rows<T, true, true>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    else dot_rows<T, true, false>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+  } else {
+    if (cnt == VC) dot_rows<T, false, true>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    else dot_rows<T, false, false>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -115,15 +142,49 @@ __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, 
   }
 }
 
+// Fold rows of partial sums (nrb x pr, row-major) into kGsGroups rows:
+// block (cx, g) sums rows g*per .. of columns 64 cx + lane, in a fixed
+// order, into out[g * pr + col].
+__device__ inline void dc_reduce_body(const double2* __restrict__ part, int nrb, int pr,
+                                      double2* __restrict__ out, int cx, int g) {
+  __shared__ double2 scratch[NT];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int per = (nrb + kGsGroups - 1) / kGsGroups;
+  const int r0 = g * per, r1 = min(nrb, r0 + per);
+  const int col = cx * 64 + lane;
+  double2 acc = z2();
+  if (col < pr) {
+    int r = r0 + wid;
+    for (; r + 3 * NW < r1; r += 4 * NW) {
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = part[(size_t)(r + u * NW) * pr + col];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = cadd(acc, v[u]);
+    }
+    for (; r < r1; r += NW) acc = cadd(acc, part[(size_t)r * pr + col]);
+  }
+  scratch[threadIdx.x] = acc;
+  __syncthreads();
+  if (wid == 0 && col < pr) {
+    double2 s = scratch[lane];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) s = cadd(s, scratch[w * 64 + lane]);
+    out[(size_t)g * pr + col] = s;
+  }
+}
+
 // Second pass of u_j and (unless FINAL) first pass of the next vector.
 // `fresh`: first step after a thick restart of the eigensolver, where the
 // columns before j already hold the restarted Rayleigh quotient (kept as is).
+// The thread updates rows r0, r0 + NT, ..., urt of them (the block's
+// reduction of the partial dots is shared by its NT * urt rows).
 template <typename T, bool FINAL>
 __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int64_t n,
                                       const double2* __restrict__ part, int nrb,
                                       const ArnoldiDev& arn, const double2* __restrict__ s_prev,
-                                      double2* __restrict__ s_cur, int fresh, int64_t r,
-                                      bool writer) {
+                                      double2* __restrict__ s_cur, int fresh, int64_t r0,
+                                      int urt, bool writer) {
   __shared__ double2 sums[2 * kMaxK + 4];
   __shared__ double2 scratch[NT];
   __shared__ double2 ct[kMaxK + 2];   // t
@@ -236,30 +297,44 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   }
   T* u = W + (int64_t)j * ldq;
   T* zv = W + (int64_t)(j + 1) * ldq;
-  if (r >= n) return;
-  double2 at = z2(), ae = z2();
-  constexpr int B = 16;   // basis loads in flight per thread
-  int i = 0;
-  for (; i + B <= j; i += B) {
-    double2 v[B];
+  for (int q = 0; q < urt; ++q) {
+    const int64_t r = r0 + (int64_t)q * NT;
+    if (r >= n) return;
+    double2 at = z2(), ae = z2();
+    constexpr int B = 16;   // basis loads in flight per thread
+    const T ru = u[r];
+    T rz;
+    if (!FINAL) rz = zv[r];
+    int i = 0;
+    for (; i + B <= j; i += B) {
+      T raw[B];
 #pragma unroll
-    for (int q = 0; q < B; ++q) v[q] = ld(W + (int64_t)(i + q) * ldq + r);
+      for (int b = 0; b < B; ++b) raw[b] = W[(int64_t)(i + b) * ldq + r];
 #pragma unroll
-    for (int q = 0; q < B; ++q) {
-      at = cadd(at, cmul(v[q], ct[i + q]));
-      if (!FINAL) ae = cadd(ae, cmul(v[q], ce[i + q]));
+      for (int b = 0; b < B; ++b) {
+        const double2 v = cvt(raw[b]);
+        at = cadd(at, cmul(v, ct[i + b]));
+        if (!FINAL) ae = cadd(ae, cmul(v, ce[i + b]));
+      }
     }
-  }
-  for (; i < j; ++i) {
-    const double2 v = ld(W + (int64_t)i * ldq + r);
-    at = cadd(at, cmul(v, ct[i]));
-    if (!FINAL) ae = cadd(ae, cmul(v, ce[i]));
-  }
-  const double2 uv = ld(u + r);
-  st(u + r, cscale(csub(uv, at), ib));                          // v_j
-  if (!FINAL) {
-    const double2 zz = ld(zv + r);
-    st(zv + r, csub(csub(cscale(zz, ib), cmul(cd, uv)), ae));   // u_{j+1}
+    if (i < j) {   // the last j - i < B vectors, with clamped (valid) addresses
+      T raw[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) raw[b] = W[(int64_t)min(i + b, j - 1) * ldq + r];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (i + b < j) {
+          const double2 v = cvt(raw[b]);
+          at = cadd(at, cmul(v, ct[i + b]));
+          if (!FINAL) ae = cadd(ae, cmul(v, ce[i + b]));
+        }
+    }
+    const double2 uv = cvt(ru);
+    st(u + r, cscale(csub(uv, at), ib));                          // v_j
+    if (!FINAL) {
+      const double2 zz = cvt(rz);
+      st(zv + r, csub(csub(cscale(zz, ib), cmul(cd, uv)), ae));   // u_{j+1}
+    }
   }
 }
 

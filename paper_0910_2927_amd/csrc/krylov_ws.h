@@ -45,7 +45,7 @@ struct KrylovWs {
   double2* ycoef;
   double2* dc;
   double2* dc2;
-  double2* gpart;      // Gram-Schmidt partial dots, gs_row_blocks(n) x (2k+2)
+  double2* gpart;      // Gram-Schmidt partial dots, gs_part_entries(gs_row_blocks(n), k)
   double2* sbuf;       // first-pass coefficients, 2 x (k+2) (alternating)
   size_t gpart_cap;    // entries of gpart
   int sbuf_k;          // k the first-pass buffers were sized for
@@ -55,7 +55,7 @@ struct KrylovWs {
 // workspace layout that runs enqueue_arnoldi).
 template <typename T>
 void carve_gs(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
-  w.gpart_cap = (size_t)gs_row_blocks(n) * (2 * k + 2);
+  w.gpart_cap = gs_part_entries(gs_row_blocks(n), k);
   w.gpart = c.template take<double2>(w.gpart_cap);
   w.sbuf = c.template take<double2>((size_t)2 * (k + 2));
   w.sbuf_k = k;
@@ -188,7 +188,7 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
   const int* skip = &w.st->breakdown;
   // every buffer the step kernels index must be there and large enough
   if (!w.W || !w.H || !w.st || !w.sbuf || !w.gpart || w.sbuf_k < k ||
-      w.gpart_cap < (size_t)gs_row_blocks(n) * (2 * k + 2) || (power == 2 && !tmp)) {
+      w.gpart_cap < gs_part_entries(gs_row_blocks(n), k) || (power == 2 && !tmp)) {
     set_error("internal: Arnoldi workspace is missing a buffer or is too small");
     return SK_ERR_WORKSPACE;
   }

@@ -71,6 +71,8 @@ __device__ inline double2 ld(const float2* p) {
   float2 v = *p;
   return mk((double)v.x, (double)v.y);
 }
+__device__ inline double2 cvt(double2 v) { return v; }
+__device__ inline double2 cvt(float2 v) { return make_double2((double)v.x, (double)v.y); }
 __device__ inline void st(double2* p, double2 v) { *p = v; }
 __device__ inline void st(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 

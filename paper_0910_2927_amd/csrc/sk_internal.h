@@ -64,18 +64,30 @@ struct TsEpiArgs {
 };
 
 // Row blocking of the Gram-Schmidt dot kernels: rows per thread such that
-// about 96 blocks of kTsThreads threads cover a vector of n rows.
+// about 1024 blocks of kTsThreads threads cover a vector of n rows (enough
+// waves in flight to cover memory latency), at most 8.
 __host__ __device__ inline int gs_rpt(int64_t n) {
-  int64_t r = (n + (int64_t)kTsThreads * 96 - 1) / ((int64_t)kTsThreads * 96);
+  int64_t r = (n + (int64_t)kTsThreads * 1024 - 1) / ((int64_t)kTsThreads * 1024);
   return (int)(r < 1 ? 1 : (r > 8 ? 8 : r));
 }
 __host__ __device__ inline int gs_row_blocks(int64_t n) {
   const int64_t rb = (int64_t)kTsThreads * gs_rpt(n);
   return (int)((n + rb - 1) / rb);
 }
+// The dot kernel leaves one row of partial sums per row block.  Up to
+// kGsDirect rows are summed by every update block itself; beyond that a
+// small reduction kernel first folds them into kGsGroups rows (the update
+// blocks would otherwise re-read all partials, a cost growing as n^2).
+constexpr int kGsDirect = 32;
+constexpr int kGsGroups = 8;
+__host__ __device__ inline bool gs_reduced(int nrb) { return nrb > kGsDirect; }
+// Entries of the partial-sum buffer for nrb row blocks and restart length k.
+__host__ __device__ inline size_t gs_part_entries(int nrb, int k) {
+  return (size_t)(nrb + kGsGroups) * (size_t)(2 * k + 2);
+}
 
 // Arnoldi step kernels with delayed reorthogonalisation (dcgs2.hip).
-// Partials need gs_row_blocks(n) x (2 k + 2) entries.
+// Partials need gs_part_entries(gs_row_blocks(n), k) entries.
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
                   const int* skip, hipStream_t s);

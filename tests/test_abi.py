@@ -74,28 +74,46 @@ def test_batched_entry_point_host_errors():
     """sign_apply_batched validates on the host before any launch."""
     from paper_0910_2927_amd import _lib
     lib = _lib.load()
-    ops = (_lib.SkOperator * 2)()
-    for o in ops:
-        o.dims[:] = [4, 4, 4, 4]
-        o.kappa = 0.25
+    sys_ = (_lib.SkBatchSystem * 2)()
+    for z, d in enumerate(sys_):
+        d.op.dims[:] = [4, 4, 4, 4]
+        d.op.kappa = 0.25
+        d.b, d.x = (1 << 20) * (z + 1), (1 << 24) * (z + 1)
     sig = (C.c_double * 2)(0.0, 1.0)
     om = (C.c_double * 2)(0.5, 0.0)
     p = _lib.SkSignParams()
     p.npoles, p.k, p.max_cycles, p.tol = 1, 10, 10, 1e-8
     p.sigma = C.cast(sig, C.POINTER(C.c_double))
     p.omega = C.cast(om, C.POINTER(C.c_double))
-    assert lib.sign_apply_batched_workspace_bytes(2, ops, None, C.byref(p)) > 0
-    assert lib.sign_apply_batched_workspace_bytes(0, ops, None, C.byref(p)) == 0
-    m = (C.c_int * 2)(0, 999)
-    assert lib.sign_apply_batched_workspace_bytes(2, ops, m, C.byref(p)) == 0
-    bp = (C.c_void_p * 2)(1 << 20, 1 << 21)
-    xp = (C.c_void_p * 2)(1 << 22, 1 << 23)
+    n2 = lib.sign_apply_batched_workspace_bytes(2, sys_, C.byref(p))
+    assert n2 > 0
+    assert lib.sign_apply_batched_workspace_bytes(1, sys_, C.byref(p)) < n2
+    assert lib.sign_apply_batched_workspace_bytes(0, sys_, C.byref(p)) == 0
+    sys_[1].k = 20                       # its own restart length: more workspace
+    assert lib.sign_apply_batched_workspace_bytes(2, sys_, C.byref(p)) > n2
+    sys_[1].k = 999
+    assert lib.sign_apply_batched_workspace_bytes(2, sys_, C.byref(p)) == 0
+    sys_[1].k = 0
+    sys_[1].m = 999
+    assert lib.sign_apply_batched_workspace_bytes(2, sys_, C.byref(p)) == 0
+    sys_[1].m = 0
     # no links
-    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
-                                C.c_void_p(1 << 30), 1 << 20, None)
+    st = lib.sign_apply_batched(2, sys_, C.byref(p), None, C.c_void_p(1 << 30), 1 << 20, None)
     assert st == _lib.SK_ERR_ARG
     # per-shift solutions are not offered by the batched solver
     p.X_shift = 1 << 24
-    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
-                                C.c_void_p(1 << 30), 1 << 20, None)
+    st = lib.sign_apply_batched(2, sys_, C.byref(p), None, C.c_void_p(1 << 30), 1 << 20, None)
     assert st == _lib.SK_ERR_ARG and b"per-shift" in lib.sk_last_error()
+
+
+def test_batched_tile_override_validation():
+    from paper_0910_2927_amd import _lib
+    lib = _lib.load()
+    assert lib.sk_batched_set_tile(0, 0) == _lib.SK_OK
+    assert lib.sk_batched_set_tile(9, 1) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(2, 0) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(4, 2) == _lib.SK_OK
+    assert lib.sk_batched_set_tile(0, 0) == _lib.SK_OK
+    a, b = C.c_int(-1), C.c_int(-1)
+    assert lib.sk_batched_last_tile(C.byref(a), C.byref(b)) == _lib.SK_OK
+    assert lib.sk_batched_last_tile(None, None) == _lib.SK_ERR_ARG

@@ -31,8 +31,8 @@ def _mixed_batch(with_c64=False):
     op1 = make_op(U1, cfg.dims, cfg.kappa, mu, with_c64=with_c64)
     b1 = si.gaussian_source(12 * V1, si.seed_for(cfg.L, "b"))
     b2 = si.z2_source(12 * V1, si.seed_for(cfg.L, "z2", 0))
-    out.append(dict(op=op1, V=V1, A=A1, b=b1, defl=None))
-    out.append(dict(op=op1, V=V1, A=A1, b=b2, defl=None))
+    out.append(dict(op=op1, V=V1, A=A1, b=b1, defl=None, sig=sig, om=om))
+    out.append(dict(op=op1, V=V1, A=A1, b=b2, defl=None, sig=sig, om=om))
     dims = (3, 4, 5, 6)
     V2 = si.lattice_volume(dims)
     U2 = si.gauge_links(dims, 0.6, 91)
@@ -41,23 +41,28 @@ def _mixed_batch(with_c64=False):
     dev = (vecs_to_dev(R, V2), vecs_to_dev(L, V2), torch.from_numpy(F).to(torch_dev()))
     out.append(dict(op=make_op(U2, dims, 0.25, mu, with_c64=with_c64), V=V2, A=A2,
                     b=si.gaussian_source(12 * V2, 92), defl=(R, L, F), defl_dev=dev))
+    out[-1]["sig"], out[-1]["om"] = rational.kl_first_order(cfg.s, 1.5)   # its own pole scale
     dims = (2, 3, 4, 5)
     V3 = si.lattice_volume(dims)
     U3 = si.gauge_links(dims, 0.5, 93)
     A3 = dirac.hw_dense(U3, dims, 0.25, mu)
     out.append(dict(op=make_op(U3, dims, 0.25, mu, with_c64=with_c64), V=V3, A=A3,
                     b=si.point_source(12 * V3, 7, 1, 2), defl=None))
+    out[-1]["sig"], out[-1]["om"] = rational.kl_first_order(cfg.s, 1.2)
     return out, sig, om, cfg
 
 
 def _solve(batch, sig, om, k, **kw):
     from paper_0910_2927_amd import api
     systems = [(s["op"], s.get("defl_dev")) for s in batch]
-    solver = api.BatchedSignSolver(systems, sig, om, k, **kw)
+    solver = api.BatchedSignSolver(systems, np.stack([s["sig"] for s in batch]),
+                                   np.stack([s["om"] for s in batch]), k, **kw)
     return solver([to_dev(s["b"], s["V"]) for s in batch])
 
 
 def test_batch_of_uneven_systems_matches_oracle():
+    """Two sources on one field, a deflated ragged lattice and a point source,
+    each lattice with its own pole scale."""
     from paper_0910_2927_amd import api
     batch, sig, om, cfg = _mixed_batch()
     announce("sign_apply_batched 4 systems (4^4 x2 shared, 3x4x5x6 m=24, 2x3x4x5) k=20 fp64")
@@ -67,10 +72,10 @@ def test_batch_of_uneven_systems_matches_oracle():
         Rm = Lm = Fm = None
         if s["defl"] is not None:
             Rm, Lm, Fm = s["defl"]
-        ref = xstar.xstar_dense(s["A"], s["b"], sig, om, Rm, Lm, Fm)
+        ref = xstar.xstar_dense(s["A"], s["b"], s["sig"], s["om"], Rm, Lm, Fm)
         err = rel(from_dev(r.x, s["V"]), ref)
         # the single-system solver on the same system
-        single = api.sign_apply(s["op"], to_dev(s["b"], s["V"]), sig, om, 20, tol=1e-11,
+        single = api.sign_apply(s["op"], to_dev(s["b"], s["V"]), s["sig"], s["om"], 20, tol=1e-11,
                                 max_cycles=400,
                                 **({} if s["defl"] is None else
                                    dict(R=s["defl_dev"][0], Lv=s["defl_dev"][1], F=s["defl_dev"][2])))
@@ -92,7 +97,7 @@ def test_batch_mixed_precision_reaches_fp64_accuracy():
         Rm = Lm = Fm = None
         if s["defl"] is not None:
             Rm, Lm, Fm = s["defl"]
-        err = rel(from_dev(r.x, s["V"]), xstar.xstar_dense(s["A"], s["b"], sig, om, Rm, Lm, Fm))
+        err = rel(from_dev(r.x, s["V"]), xstar.xstar_dense(s["A"], s["b"], s["sig"], s["om"], Rm, Lm, Fm))
         print(f"mixed system {z}: cycles={r.cycles} c64={r.cycles_c64} err={err:.2e}")
         assert err <= TOL_FP64
 
@@ -156,28 +161,133 @@ def test_batched_argument_errors():
     from paper_0910_2927_amd import _lib, api
     lib = _lib.load()
     batch, sig, om, cfg = _mixed_batch()
-    ops = (_lib.SkOperator * 2)(batch[0]["op"].struct(), batch[2]["op"].struct())
+    b0, b1 = to_dev(batch[0]["b"], batch[0]["V"]), to_dev(batch[2]["b"], batch[2]["V"])
+    x0, x1 = b0.clone(), b1.clone()
+    sys_ = (_lib.SkBatchSystem * 2)()
+    sys_[0].op, sys_[1].op = batch[0]["op"].struct(), batch[2]["op"].struct()
+    sys_[0].b, sys_[1].b = b0.data_ptr(), b1.data_ptr()
+    sys_[0].x, sys_[1].x = x0.data_ptr(), x0.data_ptr()   # two systems, one solution buffer
     p = _lib.SkSignParams()
     sg, N = api._cplx_host(sig)
     og, _ = api._cplx_host(om)
     p.npoles, p.k, p.max_cycles, p.tol = N, 10, 10, 1e-8
     p.sigma = C.cast(sg, C.POINTER(C.c_double))
     p.omega = C.cast(og, C.POINTER(C.c_double))
-    assert lib.sign_apply_batched_workspace_bytes(2, ops, None, C.byref(p)) > 0
-    b0, b1 = to_dev(batch[0]["b"], batch[0]["V"]), to_dev(batch[2]["b"], batch[2]["V"])
-    x0 = b0.clone()
-    bp = (C.c_void_p * 2)(b0.data_ptr(), b1.data_ptr())
-    xp = (C.c_void_p * 2)(x0.data_ptr(), x0.data_ptr())   # two systems, one solution buffer
-    ws = api._workspace(lib.sign_apply_batched_workspace_bytes(2, ops, None, C.byref(p)), b0.device)
-    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
-                                C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    nb = lib.sign_apply_batched_workspace_bytes(2, sys_, C.byref(p))
+    assert nb > 0
+    ws = api._workspace(nb, b0.device)
+    st = lib.sign_apply_batched(2, sys_, C.byref(p), None, C.c_void_p(ws.data_ptr()), ws.numel(), None)
     assert st == _lib.SK_ERR_ARG and b"share" in lib.sk_last_error()
-    m = (C.c_int * 2)(0, 4)
-    x1 = b1.clone()
-    xp = (C.c_void_p * 2)(x0.data_ptr(), x1.data_ptr())
-    st = lib.sign_apply_batched(2, ops, bp, xp, m, None, None, None, C.byref(p), None,
-                                C.c_void_p(ws.data_ptr()), ws.numel(), None)
+    sys_[1].x = x1.data_ptr()
+    sys_[1].m = 4                        # deflation without vectors
+    st = lib.sign_apply_batched(2, sys_, C.byref(p), None, C.c_void_p(ws.data_ptr()), ws.numel(), None)
     assert st == _lib.SK_ERR_ARG
-    st = lib.sign_apply_batched(2, ops, bp, xp, None, None, None, None, C.byref(p), None,
-                                C.c_void_p(ws.data_ptr()), 16, None)
+    sys_[1].m = 0
+    st = lib.sign_apply_batched(2, sys_, C.byref(p), None, C.c_void_p(ws.data_ptr()), 16, None)
     assert st == _lib.SK_ERR_WORKSPACE
+
+
+def test_systems_with_their_own_restart_lengths():
+    """Restart lengths 12, 20, 31 and 17 in one batch: each system as the
+    single-system solver with its own k, and against the oracle.  The last
+    one diverges (restarted FOM is not monotone; the oracle's own restarted
+    FOM diverges there too): it is reported while the others converge."""
+    from paper_0910_2927_amd import api, _lib
+    batch, sig, om, cfg = _mixed_batch()
+    ks = [12, 20, 31, 17]
+    entries = [{"op": s_["op"], "defl": s_.get("defl_dev"), "k": kz, "sigma": s_["sig"],
+                "omega": s_["om"]} for s_, kz in zip(batch, ks)]
+    announce("sign_apply_batched 4 systems, k = 12/20/31/17")
+    solver = api.BatchedSignSolver(entries, sig, om, 20, tol=1e-11, max_cycles=600)
+    res = solver([to_dev(s_["b"], s_["V"]) for s_ in batch], raise_on_error=False)
+    for z, (s_, r, kz) in enumerate(zip(batch[:3], res[:3], ks[:3])):
+        assert r.converged, z
+        single = api.sign_apply(s_["op"], to_dev(s_["b"], s_["V"]), s_["sig"], s_["om"], kz,
+                                tol=1e-11, max_cycles=600,
+                                **({} if s_["defl"] is None else
+                                   dict(R=s_["defl_dev"][0], Lv=s_["defl_dev"][1], F=s_["defl_dev"][2])))
+        Rm = Lm = Fm = None
+        if s_["defl"] is not None:
+            Rm, Lm, Fm = s_["defl"]
+        err = rel(from_dev(r.x, s_["V"]), xstar.xstar_dense(s_["A"], s_["b"], s_["sig"], s_["om"], Rm, Lm, Fm))
+        d = rel(from_dev(r.x, s_["V"]), from_dev(single.x, s_["V"]))
+        print(f"k={kz}: cycles={r.cycles} (single {single.cycles}) matvecs={r.matvecs} "
+              f"err={err:.2e} vs single {d:.2e}")
+        assert abs(r.cycles - single.cycles) <= 1
+        assert err <= TOL_FP64 and d <= 1e-9
+    s3 = batch[3]
+    _, info = krylov.restarted_fom_lr(lambda v: s3["A"] @ v, s3["b"], s3["sig"], s3["om"], 17,
+                                      tol_update=1e-11, max_cycles=600)
+    print(f"k=17: GPU converged={res[3].converged} after {res[3].cycles} cycles; "
+          f"oracle converged={info['converged']} after {info['cycles']}")
+    assert not info["converged"]
+    assert not res[3].converged and res[3].status == _lib.SK_ERR_NOCONV
+
+
+def test_row_blocking_does_not_change_results():
+    """Every tile the tuner may pick gives the same solutions to rounding,
+    and the tuner's pick is one of them."""
+    from paper_0910_2927_amd import api, _lib
+    lib = _lib.load()
+    dims = (6, 6, 6, 6)
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.5, 77)
+    sig, om = rational.kl_first_order(8, 1.5)
+    op = make_op(U, dims, 0.25, 0.3)
+    srcs = [to_dev(si.z2_source(12 * V, 500 + i), V) for i in range(6)]
+    outs = {}
+    try:
+        for tile in [(1, 1), (2, 1), (8, 1), (4, 2), (8, 4), (0, 0)]:
+            assert lib.sk_batched_set_tile(*tile) == _lib.SK_OK
+            announce(f"sign_apply_batched 6^4 x6 tile {tile}")
+            solver = api.BatchedSignSolver([(op, None)] * 6, sig, om, 24, tol=1e-10, max_cycles=300)
+            res = solver(srcs)
+            assert all(r.converged for r in res)
+            outs[tile] = [r.x.clone() for r in res]
+            if tile == (0, 0):
+                print("tuner picked", solver.tile)
+                assert solver.tile["dot_rows_per_thread"] in (1, 2, 4, 8)
+                assert solver.tile["update_rows_per_thread"] in (1, 2, 4)
+            else:
+                assert solver.tile == {"dot_rows_per_thread": tile[0],
+                                       "update_rows_per_thread": tile[1]}
+    finally:
+        lib.sk_batched_set_tile(0, 0)
+    ref = outs[(1, 1)]
+    for tile, xs in outs.items():
+        for a, b in zip(xs, ref):
+            d = rel(from_dev(a, V), from_dev(b, V))
+            assert d <= 1e-10, (tile, d)
+
+
+def test_deflated_lattices_whose_row_blocking_is_not_monotone():
+    """8x8x8x4 (n = 24576, one row per thread, 96 row blocks) next to the
+    larger 6x6x6x10 (n = 25920, two rows per thread, 51 row blocks): the
+    deflation dots of the smaller system need more row blocks than the
+    largest system; every block must still be reduced.  The projector is
+    built from random orthonormal R = L (F = I, projection of the source
+    only), which both solvers take as given."""
+    import torch
+    from paper_0910_2927_amd import api
+    sig, om = rational.kl_first_order(5, 1.5)
+    entries, bs, singles = [], [], []
+    for dims, seed in (((8, 8, 8, 4), 41), ((6, 6, 6, 10), 42)):
+        V = si.lattice_volume(dims)
+        U = si.gauge_links(dims, 0.5, seed)
+        op = make_op(U, dims, 0.25, 0.3)
+        Q = np.linalg.qr(si.gaussian_source(12 * V * 8, seed + 7).reshape(12 * V, 8))[0]
+        R = vecs_to_dev(Q, V)
+        F = torch.eye(8, dtype=torch.complex128, device=R.device)
+        b = to_dev(si.gaussian_source(12 * V, seed + 100), V)
+        entries.append((op, (R, R, F)))
+        bs.append(b)
+        announce(f"sign_apply {dims} with an 8-dimensional projector")
+        singles.append(api.sign_apply(op, b, sig, om, 20, tol=1e-11, max_cycles=400, R=R, Lv=R, F=F,
+                                      project_each_cycle=False))
+    announce("sign_apply_batched 8x8x8x4 + 6x6x6x10, m=8")
+    res = api.BatchedSignSolver(entries, sig, om, 20, tol=1e-11, max_cycles=400,
+                                project_each_cycle=False)(bs)
+    for r, s_ in zip(res, singles):
+        d = float((r.x - s_.x).norm() / s_.x.norm())
+        print(f"batched vs single: {d:.2e}, cycles {r.cycles} vs {s_.cycles}")
+        assert r.converged and d <= 1e-9
