@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the multi-source leg (84 sources on 6^4, 8^4, 10^4)")
     ap.add_argument("--batched-only", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the 16^4 / 24^4 bandwidth sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE hardware counters) and exit")
@@ -50,6 +52,95 @@ def parse():
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+KERNEL_SOURCES = ("dcgs2_dev.h", "dcgs2.hip", "sk_common.h", "sk_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 of the sources that define the Gram-Schmidt dot kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_0910_2927_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def load_counters(path):
+    """key: value lines of a committed hardware-counter summary."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", " ", "|", "`")):
+            k, v = line.split(":", 1)
+            v = v.strip()
+            try:
+                out[k.strip()] = float(v)
+            except ValueError:
+                out[k.strip()] = v
+    return out
+
+
+def kernel_times(lib, solver, b, x, stream):
+    """Per-class kernel times of one solve (HIP events around each launch)."""
+    import torch
+    from paper_0910_2927_amd import _lib
+    times = _lib.SkKernelTimes()
+    st = _lib.SkStats()
+    st.times = C.pointer(times)
+    status = lib.sign_apply(C.byref(solver.opstruct), C.byref(solver.params), C.c_void_p(b.data_ptr()),
+                            C.c_void_p(x.data_ptr()), C.byref(st), C.c_void_p(solver.ws.data_ptr()),
+                            solver.ws.numel(), C.c_void_p(stream.cuda_stream))
+    if status not in (_lib.SK_OK, _lib.SK_ERR_NOCONV):
+        _lib.check(status)
+    torch.cuda.synchronize()
+    kern = {}
+    for i, name in enumerate(_lib.SK_KERNEL_CLASSES):
+        if times.launches[i]:
+            kern[name] = {"ms": times.ms[i], "launches": int(times.launches[i]),
+                          "avg_us": 1e3 * times.ms[i] / times.launches[i],
+                          "bytes_per_launch": times.bytes[i] / times.launches[i],
+                          "GBs": times.bytes[i] / (times.ms[i] * 1e-3) / 1e9 if times.ms[i] > 0 else None}
+    return kern, st
+
+
+def sweep_leg():
+    """Stencil and Gram-Schmidt bandwidth where the basis no longer fits in
+    the 256 MB last-level cache: one restart cycle (k = 16) on 16^4 and 24^4
+    lattices, complex double and complex float."""
+    import torch
+    import skinputs as si
+    from paper_0910_2927_amd import api, _lib
+    lib = _lib.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = []
+    for L in (16, 24):
+        dims = (L, L, L, L)
+        V = L ** 4
+        U = si.gauge_links(dims, 0.7, si.seed_for(L, "gauge"))
+        links = torch.from_numpy(si.links_soa_from_canonical(U).reshape(-1)).to(dev)
+        del U
+        op = api.WilsonOperator(links, dims, 0.25, 0.3, True, links64=links.to(torch.complex64))
+        b = torch.from_numpy(si.soa_from_canonical(si.gaussian_source(12 * V, si.seed_for(L, "b")), V)).to(dev)
+        sig, om = api.kl_poles(8, 2.0)
+        for prec in ("fp64", "mixed_c64_only"):
+            sv = api.SignSolver(op, sig, om, 16, tol=1e-10, max_cycles=1, precision=prec)
+            x = torch.empty_like(b)
+            kernel_times(lib, sv, b, x, stream)          # warm-up
+            kern, _ = kernel_times(lib, sv, b, x, stream)
+            row = {"lattice": f"{L}^4", "n": 12 * V, "basis": "c128" if prec == "fp64" else "c64"}
+            for name in ("stencil", "gs_dot", "gs_upd_dot"):
+                row[name + "_GBs"] = kern[name]["GBs"]
+                row[name + "_avg_us"] = kern[name]["avg_us"]
+            out.append(row)
+            log(f"sweep {L}^4 {row['basis']}: stencil {row['stencil_GBs']:.0f}, dots "
+                f"{row['gs_dot_GBs']:.0f}, update {row['gs_upd_dot_GBs']:.0f} GB/s")
+            del sv
+        del op, links, b
+        torch.cuda.empty_cache()
+    return out
 
 
 def batched_leg(args, log_prefix="batched"):
@@ -243,27 +334,25 @@ def main():
     log(f"{args.steps} solves in {sec:.4f} s (wall {wall:.4f} s); cycles/solve={cycles[-1]} "
         f"(complex float {res.cycles_c64}) matvecs={res.matvecs}")
 
-    # ---- per-kernel timing of one more solve (HIP events on the solve's stream)
-    times = _lib.SkKernelTimes()
-    st = _lib.SkStats()
-    st.times = C.pointer(times)
+    # ---- per-kernel timing (HIP events around every launch on the solve's
+    # stream, plain launches): one more solve as timed, and one whose cycles
+    # all use the complex-float basis, which gives the dominant kernel
     lib = _lib.load()
-    status = lib.sign_apply(C.byref(solver.opstruct), C.byref(solver.params), C.c_void_p(bd.data_ptr()),
-                            C.c_void_p(x.data_ptr()), C.byref(st), C.c_void_p(solver.ws.data_ptr()),
-                            solver.ws.numel(), C.c_void_p(stream.cuda_stream))
-    _lib.check(status)
-    torch.cuda.synchronize()
-    kern = {}
-    for i, name in enumerate(_lib.SK_KERNEL_CLASSES):
-        if times.launches[i]:
-            kern[name] = {"ms": times.ms[i], "launches": int(times.launches[i]),
-                          "avg_us": 1e3 * times.ms[i] / times.launches[i],
-                          "GBs": times.bytes[i] / (times.ms[i] * 1e-3) / 1e9 if times.ms[i] > 0 else None}
-    dom = max(kern, key=lambda k_: kern[k_]["ms"])
-    dom_i = _lib.SK_KERNEL_CLASSES.index(dom)
-    achieved = times.bytes[dom_i] / (times.ms[dom_i] * 1e-3) / 1e9
+    kern, _ = kernel_times(lib, solver, bd, x, stream)
     log("kernel classes: " + ", ".join(f"{k_}: {v['ms']:.2f} ms/{v['launches']} "
                                        f"({v['GBs'] or 0:.0f} GB/s)" for k_, v in kern.items()))
+    x64 = torch.empty_like(bd)
+    solver_c64 = api.SignSolver(op, sigma, omega, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles,
+                                precision="mixed_c64_only", R=R, Lv=Lv, F=F)
+    kern_c64, _ = kernel_times(lib, solver_c64, bd, x64, stream)
+    dom = "gs_dot"
+    achieved = kern_c64[dom]["GBs"]
+    counters = load_counters(os.path.join(ROOT, "profiles", "k_dc_dot_c64_10x4_counters.txt"))
+    traffic = None
+    if counters and counters.get("source_sha256") == kernel_source_hash():
+        traffic = counters["traffic_bytes_per_launch"] / (kern_c64[dom]["avg_us"] * 1e-6) / 1e9
+    log(f"dominant kernel (complex-float Gram-Schmidt dots): {achieved:.0f} GB/s algorithmic, "
+        f"{kern_c64[dom]['avg_us']:.1f} us per launch")
 
     # ---- parity against the oracle's stored sample, when one exists for this setup
     err = None
@@ -300,6 +389,7 @@ def main():
         log(f"cpu oracle: {tc:.2f} s per cycle on {cores} cores")
 
     batched = None if args.no_batched else batched_leg(args)
+    sweep = None if args.no_sweep else sweep_leg()
 
     out = {
         "metric": "sign(H_W)b solves/s at 10^4, mu=0.3, rel err 1e-8; stencil HBM GB/s",
@@ -317,9 +407,15 @@ def main():
         "stencil": {"GBs": kern.get("stencil", {}).get("GBs"),
                     "avg_us": kern.get("stencil", {}).get("avg_us"),
                     "note": "algorithmic bytes (12 in + 36 link + 12 out complex per site) / time"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_dc_dot, complex-float basis (Gram-Schmidt dots V^H [u z])",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_launch": kern_c64[dom]["bytes_per_launch"],
+                     "avg_us": kern_c64[dom]["avg_us"], "launches": kern_c64[dom]["launches"]},
         "kernels": kern,
+        "kernels_complex_float": kern_c64,
+        "bandwidth_sweep": sweep,
         "cpu_baseline": cpu,
         "batched": batched,
     }

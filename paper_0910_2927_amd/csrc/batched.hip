@@ -182,8 +182,9 @@ struct BTile {
   int rpt;
   int urt;
 };
-__host__ __device__ inline int brow_blocks(int64_t n, int rpt) {
-  const int64_t rb = (int64_t)kBNT * rpt;
+// row blocks of rpt row packs of `pack` rows per thread
+__host__ __device__ inline int brow_blocks(int64_t n, int rpt, int pack = 1) {
+  const int64_t rb = (int64_t)kBNT * rpt * pack;
   return (int)((n + rb - 1) / rb);
 }
 
@@ -195,18 +196,19 @@ __global__ __launch_bounds__(kBNT) void k_bdot(const BSys* __restrict__ sys, con
   const int z = blockIdx.z;
   const BSys& S = sys[z];
   if (j > S.k || !live(S, act, z)) return;
-  if ((int)blockIdx.x >= brow_blocks(S.n, tile.rpt)) return;
+  if ((int)blockIdx.x >= brow_blocks(S.n, tile.rpt, Pk<T>::P)) return;
   dc_dot_body<T>(basis<T>(S), S.n, j, j < S.k ? 1 : 0, S.n, tile.rpt, S.gpart, blockIdx.x, blockIdx.y);
 }
 
 // Fold the dot partials of systems with many row blocks into kGsGroups rows
 // (stored after them), so that update blocks read a few rows only.
+template <typename T>
 __global__ __launch_bounds__(kBNT) void k_breduce(const BSys* __restrict__ sys, const int* __restrict__ act,
                                                   int j, BTile tile) {
   const int z = blockIdx.z;
   const BSys& S = sys[z];
   if (j > S.k || !live(S, act, z)) return;
-  const int nrb = brow_blocks(S.n, tile.rpt);
+  const int nrb = brow_blocks(S.n, tile.rpt, Pk<T>::P);
   if (!gs_reduced(nrb)) return;
   const int pr = 2 * j + 2;
   dc_reduce_body(S.gpart, nrb, pr, S.gpart + (size_t)nrb * pr, blockIdx.x, blockIdx.y);
@@ -219,10 +221,10 @@ __global__ __launch_bounds__(kBNT) void k_bupdate(const BSys* __restrict__ sys,
   const int z = blockIdx.z;
   const BSys& S = sys[z];
   if ((FINAL ? j != S.k : j >= S.k) || !live(S, act, z)) return;
-  const int64_t r0 = (int64_t)blockIdx.x * kBNT * tile.urt;
-  if (r0 >= S.n) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kBNT * tile.urt;   // in row packs
+  if (r0 * Pk<T>::P >= S.n) return;
   const int k = S.k;
-  const int nrb = brow_blocks(S.n, tile.rpt);
+  const int nrb = brow_blocks(S.n, tile.rpt, Pk<T>::P);
   const double2* src = gs_reduced(nrb) ? S.gpart + (size_t)nrb * (2 * j + 2) : S.gpart;
   dc_update_body<T, FINAL>(basis<T>(S), S.n, j, S.n, src, gs_reduced(nrb) ? kGsGroups : nrb, S.arn,
                            S.sbuf + (size_t)((j - 1) & 1) * (k + 2), S.sbuf + (size_t)(j & 1) * (k + 2),
@@ -533,14 +535,14 @@ hipStream_t batch_capture_stream() {
 // stepping, and the final pass of systems whose restart length is j.
 template <typename T>
 int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
-  const int maxrb = brow_blocks(P.nmax, tile.rpt);
-  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt);
+  const int maxrb = brow_blocks(P.nmax, tile.rpt, Pk<T>::P);
+  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt, Pk<T>::P);
   hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
                      P.dsys, P.act, j, tile);
   SK_LAUNCH(hipGetLastError());
   if (gs_reduced(maxrb)) {
-    hipLaunchKernelGGL(k_breduce, dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                       P.act, j, tile);
+    hipLaunchKernelGGL((k_breduce<T>), dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s,
+                       P.dsys, P.act, j, tile);
     SK_LAUNCH(hipGetLastError());
   }
   if (j < P.kmax) {
@@ -559,14 +561,14 @@ int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
 // One non-final Gram-Schmidt step for the tuner.
 template <typename T>
 int enqueue_bgs_step(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
-  const int maxrb = brow_blocks(P.nmax, tile.rpt);
-  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt);
+  const int maxrb = brow_blocks(P.nmax, tile.rpt, Pk<T>::P);
+  const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt, Pk<T>::P);
   hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
                      P.dsys, P.act, j, tile);
   SK_LAUNCH(hipGetLastError());
   if (gs_reduced(maxrb)) {
-    hipLaunchKernelGGL(k_breduce, dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                       P.act, j, tile);
+    hipLaunchKernelGGL((k_breduce<T>), dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s,
+                       P.dsys, P.act, j, tile);
     SK_LAUNCH(hipGetLastError());
   }
   hipLaunchKernelGGL((k_bupdate<T, false>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act, j,

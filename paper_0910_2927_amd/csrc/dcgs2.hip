@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ld
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
                   const int* skip, hipStream_t s) {
-  const int nrb = gs_row_blocks(n);
+  const int nrb = gs_row_blocks(n, Pk<T>::P);
   dim3 grid(nrb, j > 0 ? (j + kVC - 1) / kVC : 1);
   hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
                      part, skip);
@@ -82,11 +82,12 @@ template <typename T>
 hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const double2* part,
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
                      const int* skip, hipStream_t s) {
-  const int nrb = gs_row_blocks(n);                  // rows of partials (the dot kernel's grid)
+  const int nrb = gs_row_blocks(n, Pk<T>::P);         // rows of partials (the dot kernel's grid)
   const int pr = 2 * j + 2;
   const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
   const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
-  const unsigned nb = (unsigned)((n + kNT - 1) / kNT);  // one row per thread here
+  const int64_t rows_per_block = (int64_t)kNT * Pk<T>::P;   // one row pack per thread here
+  const unsigned nb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
   if (final_pass)
     hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);

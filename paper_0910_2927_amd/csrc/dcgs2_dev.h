@@ -14,6 +14,33 @@ constexpr int VC = 8;
 
 __device__ inline double2 z2() { return make_double2(0.0, 0.0); }
 
+// Row packs: a thread loads P consecutive rows of a vector with one 16-byte
+// load (P = 2 for complex float).  n = 12 V is even and every vector starts
+// 16-byte aligned, so packs never straddle the end or a vector boundary.
+template <typename T> struct Pk;
+template <> struct Pk<double2> {
+  using type = double2;
+  static constexpr int P = 1;
+  __device__ static double2 get(const double2& v, int) { return v; }
+  __device__ static void set(double2& v, int, double2 x) { v = x; }
+};
+template <> struct Pk<float2> {
+  using type = float4;
+  static constexpr int P = 2;
+  __device__ static double2 get(const float4& v, int p) {
+    return p == 0 ? make_double2((double)v.x, (double)v.y) : make_double2((double)v.z, (double)v.w);
+  }
+  __device__ static void set(float4& v, int p, double2 x) {
+    if (p == 0) {
+      v.x = (float)x.x;
+      v.y = (float)x.y;
+    } else {
+      v.z = (float)x.x;
+      v.w = (float)x.y;
+    }
+  }
+};
+
 __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, int pr, double2* sums,
                                    double2* scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -43,41 +70,47 @@ __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, i
   }
 }
 
-// Rows of one dot block: every load of a row is issued before any of it is
-// used (raw values, converted afterwards), so a wave has VC + 2 loads in
-// flight.  FULL: the chunk holds VC vectors (no masking); otherwise
-// vectors past cnt re-read a valid vector and are masked out.
+// Rows of one dot block: every load of a row pack is issued before any of
+// it is used, so a wave has VC + 2 loads in flight.  FULL: the chunk holds
+// VC vectors (no masking); otherwise vectors past cnt re-read a valid
+// vector and are masked out.  base, rpt count packs.
 template <typename T, bool HAS_Z, bool FULL>
 __device__ inline void dot_rows(const T* __restrict__ W, int64_t ldq, int j, int i0, int cnt, int64_t n,
                                 int rpt, int64_t base, bool first, double2 (&at)[VC], double2 (&ap)[VC],
                                 double2& aa, double2& ag) {
-  const T* u = W + (int64_t)j * ldq;
-  const T* zv = u + ldq;
+  using K = Pk<T>;
+  using PT = typename K::type;
+  const PT* u = reinterpret_cast<const PT*>(W + (int64_t)j * ldq);
+  const PT* zv = reinterpret_cast<const PT*>(W + (int64_t)(j + 1) * ldq);
   const int last = cnt > 0 ? cnt - 1 : 0;
-  const T* vb[VC];
+  const PT* vb[VC];
 #pragma unroll
-  for (int c = 0; c < VC; ++c) vb[c] = W + (int64_t)(i0 + (FULL ? c : min(c, last))) * ldq;
+  for (int c = 0; c < VC; ++c)
+    vb[c] = reinterpret_cast<const PT*>(W + (int64_t)(i0 + (FULL ? c : min(c, last))) * ldq);
   for (int q = 0; q < rpt; ++q) {
-    const int64_t r = base + (int64_t)q * NT;
-    if (r >= n) break;
-    T raw[VC];
-    const T ru = u[r];
-    T rz;
-    if (HAS_Z) rz = zv[r];
+    const int64_t rp = base + (int64_t)q * NT;
+    if (rp * K::P >= n) break;
+    PT raw[VC];
+    const PT ru = u[rp];
+    PT rz;
+    if (HAS_Z) rz = zv[rp];
 #pragma unroll
-    for (int c = 0; c < VC; ++c) raw[c] = vb[c][r];
-    const double2 uv = cvt(ru);
-    const double2 zz = HAS_Z ? cvt(rz) : z2();
+    for (int c = 0; c < VC; ++c) raw[c] = vb[c][rp];
 #pragma unroll
-    for (int c = 0; c < VC; ++c)
-      if (FULL || c < cnt) {
-        const double2 vv = cvt(raw[c]);
-        at[c] = cadd(at[c], cconjmul(vv, uv));
-        if (HAS_Z) ap[c] = cadd(ap[c], cconjmul(vv, zz));
+    for (int p = 0; p < K::P; ++p) {
+      const double2 uv = K::get(ru, p);
+      const double2 zz = HAS_Z ? K::get(rz, p) : z2();
+#pragma unroll
+      for (int c = 0; c < VC; ++c)
+        if (FULL || c < cnt) {
+          const double2 vv = K::get(raw[c], p);
+          at[c] = cadd(at[c], cconjmul(vv, uv));
+          if (HAS_Z) ap[c] = cadd(ap[c], cconjmul(vv, zz));
+        }
+      if (first) {
+        aa.x += cabs2(uv);
+        if (HAS_Z) ag = cadd(ag, cconjmul(uv, zz));
       }
-    if (first) {
-      aa.x += cabs2(uv);
-      if (HAS_Z) ag = cadd(ag, cconjmul(uv, zz));
     }
   }
 }
@@ -95,7 +128,7 @@ __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, 
   double2 aa = z2(), ag = z2();
 #pragma unroll
   for (int q = 0; q < VC; ++q) at[q] = ap[q] = z2();
-  const int64_t base = (int64_t)rb * NT * rpt + threadIdx.x;
+  const int64_t base = (int64_t)rb * NT * rpt + threadIdx.x;   // in packs
   const bool first = ch == 0;
   if (has_z) {
     if (cnt == VC) dot_rows<T, true, true>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
@@ -177,8 +210,8 @@ __device__ inline void dc_reduce_body(const double2* __restrict__ part, int nrb,
 // Second pass of u_j and (unless FINAL) first pass of the next vector.
 // `fresh`: first step after a thick restart of the eigensolver, where the
 // columns before j already hold the restarted Rayleigh quotient (kept as is).
-// The thread updates rows r0, r0 + NT, ..., urt of them (the block's
-// reduction of the partial dots is shared by its NT * urt rows).
+// The thread updates row packs r0, r0 + NT, ..., urt of them (the block's
+// reduction of the partial dots is shared by its NT * urt packs).
 template <typename T, bool FINAL>
 __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int64_t n,
                                       const double2* __restrict__ part, int nrb,
@@ -295,46 +328,58 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
       }
     __syncthreads();
   }
-  T* u = W + (int64_t)j * ldq;
-  T* zv = W + (int64_t)(j + 1) * ldq;
+  using K = Pk<T>;
+  using PT = typename K::type;
+  PT* u = reinterpret_cast<PT*>(W + (int64_t)j * ldq);
+  PT* zv = reinterpret_cast<PT*>(W + (int64_t)(j + 1) * ldq);
   for (int q = 0; q < urt; ++q) {
-    const int64_t r = r0 + (int64_t)q * NT;
-    if (r >= n) return;
-    double2 at = z2(), ae = z2();
+    const int64_t rp = r0 + (int64_t)q * NT;
+    if (rp * K::P >= n) return;
+    double2 at[K::P], ae[K::P];
+#pragma unroll
+    for (int p = 0; p < K::P; ++p) at[p] = ae[p] = z2();
     constexpr int B = 16;   // basis loads in flight per thread
-    const T ru = u[r];
-    T rz;
-    if (!FINAL) rz = zv[r];
+    const PT ru = u[rp];
+    PT rz;
+    if (!FINAL) rz = zv[rp];
     int i = 0;
     for (; i + B <= j; i += B) {
-      T raw[B];
+      PT raw[B];
 #pragma unroll
-      for (int b = 0; b < B; ++b) raw[b] = W[(int64_t)(i + b) * ldq + r];
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const double2 v = cvt(raw[b]);
-        at = cadd(at, cmul(v, ct[i + b]));
-        if (!FINAL) ae = cadd(ae, cmul(v, ce[i + b]));
-      }
-    }
-    if (i < j) {   // the last j - i < B vectors, with clamped (valid) addresses
-      T raw[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) raw[b] = W[(int64_t)min(i + b, j - 1) * ldq + r];
+      for (int b = 0; b < B; ++b) raw[b] = reinterpret_cast<const PT*>(W + (int64_t)(i + b) * ldq)[rp];
 #pragma unroll
       for (int b = 0; b < B; ++b)
-        if (i + b < j) {
-          const double2 v = cvt(raw[b]);
-          at = cadd(at, cmul(v, ct[i + b]));
-          if (!FINAL) ae = cadd(ae, cmul(v, ce[i + b]));
+#pragma unroll
+        for (int p = 0; p < K::P; ++p) {
+          const double2 v = K::get(raw[b], p);
+          at[p] = cadd(at[p], cmul(v, ct[i + b]));
+          if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + b]));
         }
     }
-    const double2 uv = cvt(ru);
-    st(u + r, cscale(csub(uv, at), ib));                          // v_j
-    if (!FINAL) {
-      const double2 zz = cvt(rz);
-      st(zv + r, csub(csub(cscale(zz, ib), cmul(cd, uv)), ae));   // u_{j+1}
+    if (i < j) {   // the last j - i < B vectors, with clamped (valid) addresses
+      PT raw[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        raw[b] = reinterpret_cast<const PT*>(W + (int64_t)min(i + b, j - 1) * ldq)[rp];
+#pragma unroll
+      for (int b = 0; b < B; ++b)
+        if (i + b < j)
+#pragma unroll
+          for (int p = 0; p < K::P; ++p) {
+            const double2 v = K::get(raw[b], p);
+            at[p] = cadd(at[p], cmul(v, ct[i + b]));
+            if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + b]));
+          }
     }
+    PT vo, uo;
+#pragma unroll
+    for (int p = 0; p < K::P; ++p) {
+      const double2 uv = K::get(ru, p);
+      K::set(vo, p, cscale(csub(uv, at[p]), ib));                                 // v_j
+      if (!FINAL) K::set(uo, p, csub(csub(cscale(K::get(rz, p), ib), cmul(cd, uv)), ae[p]));   // u_{j+1}
+    }
+    u[rp] = vo;
+    if (!FINAL) zv[rp] = uo;
   }
 }
 

@@ -78,10 +78,30 @@ __device__ inline void st(float2* p, double2 v) { *p = make_float2((float)v.x, (
 
 // ----------------------------------------------------------------- reductions
 // Wave64 sum of a double (all lanes receive the result).
+// Cross-lane move of a double with a DPP pattern (both 32-bit halves);
+// lanes outside ROW_MASK receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane.  Register-level
+// data movement (DPP) instead of LDS permutes: within quads (lane ^ 1,
+// lane ^ 2), rotations by 4 and 8 within each row of 16 lanes, then row
+// broadcasts 15 -> row 1, 3 and 31 -> rows 2, 3, which leave the total in
+// lane 63.  The order of additions is fixed.
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_move<0xB1>(v);         // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);         // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);        // row_ror:4
+  v += dpp_move<0x128>(v);        // row_ror:8
+  v += dpp_move<0x142, 0xA>(v);   // row_bcast:15
+  v += dpp_move<0x143, 0xC>(v);   // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 inline int64_t volume_of(const sk_operator* op) {

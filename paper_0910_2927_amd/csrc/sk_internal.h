@@ -70,8 +70,10 @@ __host__ __device__ inline int gs_rpt(int64_t n) {
   int64_t r = (n + (int64_t)kTsThreads * 1024 - 1) / ((int64_t)kTsThreads * 1024);
   return (int)(r < 1 ? 1 : (r > 8 ? 8 : r));
 }
-__host__ __device__ inline int gs_row_blocks(int64_t n) {
-  const int64_t rb = (int64_t)kTsThreads * gs_rpt(n);
+// pack: consecutive rows a thread loads at once (2 for complex float: one
+// 16-byte load); 1 gives the most row blocks, for sizing buffers.
+__host__ __device__ inline int gs_row_blocks(int64_t n, int pack = 1) {
+  const int64_t rb = (int64_t)kTsThreads * gs_rpt(n) * pack;
   return (int)((n + rb - 1) / rb);
 }
 // The dot kernel leaves one row of partial sums per row block.  Up to
