@@ -183,14 +183,15 @@ typedef struct {
 
 /* Kernel classes of a solve, for the optional per-kernel timing. */
 typedef enum {
-  SK_K_STENCIL = 0,     /* w = H_W v */
-  SK_K_GS_DOT = 1,      /* Gram-Schmidt pass 1: h = V^H w */
-  SK_K_GS_UPD_DOT = 2,  /* w -= V h, then pass 2 dots V^H w */
-  SK_K_GS_UPD_NORM = 3, /* w -= V h2, then ||w|| */
+  SK_K_STENCIL = 0,     /* z = H_W u */
+  SK_K_GS_DOT = 1,      /* Gram-Schmidt dots V_j^H [u z], u^H u, u^H z (one kernel) */
+  SK_K_GS_UPD_DOT = 2,  /* v_j and the next first-pass vector from one pass over V_j */
+  SK_K_GS_UPD_NORM = 3, /* final second pass of the last vector (dots + update) */
   SK_K_SMALL = 4,       /* shifted Hessenberg solves */
   SK_K_SOL_UPDATE = 5,  /* x += V_k u (and per-shift X) */
   SK_K_PROJECT = 6,     /* deflation projection / restart vector */
-  SK_K_COUNT = 7
+  SK_K_GS_REDUCE = 7,   /* folding of the dot partial sums (large n only) */
+  SK_K_COUNT = 8
 } sk_kernel_class;
 
 /* Per-class kernel time (HIP events on the call's stream, summed over the
@@ -290,17 +291,18 @@ int sign_apply_batched(int nsys, const sk_batch_system* sys, const sk_sign_param
                        sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
- * Row blocking the batched solver's tuner chose for the calling thread's
+ * Launch shapes the batched solver's tuner chose for the calling thread's
  * last sign_apply_batched call: rows per thread of the Gram-Schmidt dot
- * kernel and of the update kernel.  The tuner times every candidate on the
- * first call for a batch shape (number and sizes of the systems, k,
- * precision) and caches the fastest for the life of the process.
- * Host only; returns SK_ERR_ARG for NULL pointers.
+ * kernel and of the update kernel, and right-hand sides per stencil block.
+ * The tuner times every candidate on the first call for a batch shape
+ * (number and sizes of the systems, their k, precision) and caches the
+ * fastest for the life of the process.  Host only; SK_ERR_ARG for NULL.
  */
-int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update);
-/* Fix the row blocking of later batched calls (process-wide; 1..8 rows per
- * thread each), or hand it back to the tuner with (0, 0).  Host only. */
-int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update);
+int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update, int* rhs_per_block);
+/* Fix the shapes of later batched calls (process-wide; 1..8 rows per thread
+ * each, 1..64 right-hand sides per block), or hand them back to the tuner
+ * with (0, 0, 0).  Host only. */
+int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update, int rhs_per_block);
 
 /*
  * Deflation data for Algorithm 1: the m "critical" eigenvalues of H_W

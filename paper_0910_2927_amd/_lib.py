@@ -47,7 +47,7 @@ class SkSignParams(C.Structure):
 
 
 SK_KERNEL_CLASSES = ["stencil", "gs_dot", "gs_upd_dot", "gs_upd_norm", "small", "sol_update",
-                     "project"]
+                     "project", "gs_reduce"]
 
 
 class SkKernelTimes(C.Structure):
@@ -115,8 +115,8 @@ SIGNATURES = [
                                                         C.POINTER(SkSignParams)]),
     ("sign_apply_batched", C.c_int, [C.c_int, C.POINTER(SkBatchSystem), C.POINTER(SkSignParams),
                                      C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
-    ("sk_batched_last_tile", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int)]),
-    ("sk_batched_set_tile", C.c_int, [C.c_int, C.c_int]),
+    ("sk_batched_last_tile", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    ("sk_batched_set_tile", C.c_int, [C.c_int, C.c_int, C.c_int]),
     ("sign_apply_backward_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator),
                                                          C.POINTER(SkSignParams)]),
     ("sign_apply_backward", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,

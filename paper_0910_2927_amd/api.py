@@ -410,9 +410,10 @@ class BatchedSignSolver:
                                              _ptr(self.ws), self.ws.numel(), _stream())
         if raise_on_error and status != L.SK_OK:
             L.check(status)
-        a, b_ = C.c_int(), C.c_int()
-        self.lib.sk_batched_last_tile(C.byref(a), C.byref(b_))
-        self.tile = {"dot_rows_per_thread": a.value, "update_rows_per_thread": b_.value}
+        a, b_, c_ = C.c_int(), C.c_int(), C.c_int()
+        self.lib.sk_batched_last_tile(C.byref(a), C.byref(b_), C.byref(c_))
+        self.tile = {"dot_rows_per_thread": a.value, "update_rows_per_thread": b_.value,
+                     "rhs_per_stencil_block": c_.value}
         out = []
         for z in range(self.nsys):
             nc = min(st[z].cycles, self.hist_cap)

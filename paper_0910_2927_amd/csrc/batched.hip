@@ -25,7 +25,16 @@ constexpr int kBNT = kTsThreads;
 constexpr int kMaxGroupRhs = 64;
 constexpr int kSites = 64;            // sites per stencil block
 constexpr int kBStencilThreads = 512; // one wave per hop
-constexpr int kRhsPerBlock = 4;       // right-hand sides per stencil block (links held across them)
+
+// Launch shapes chosen by the tuner: rows per thread of the Gram-Schmidt
+// dot kernel (hence row blocks of partial sums) and of the update kernel
+// (both in row packs), and right-hand sides per stencil block (the links of
+// a block's sites are loaded once for all of them).
+struct BTile {
+  int rpt;
+  int urt;
+  int rhs;
+};
 
 // One system of the batch.
 struct BSys {
@@ -74,15 +83,28 @@ __device__ inline bool live(const BSys& S, const int* act, int z) {
 }
 
 // ---- stencil: z = A u_j for every live system of a group
+// Hop H of one site from the neighbour's 12 components already in registers:
+// project to the half spinor, multiply by the link (in registers), scale.
 template <int H, typename T>
-__device__ inline void bhop(double2 (*hs)[64], const T* in, const double2 (&u)[3][3], int V, int nb,
-                            double fac, int lane) {
-  double2 u0[3], u1[3];
-  half_with_link<(H >> 1), (H & 1) ? 1 : -1>(u0, u1, in, V, nb, u, fac);
+__device__ inline void bhop(double2 (*hs)[64], const T (&raw)[12], const double2 (&u)[3][3], double fac,
+                            int lane) {
+  using PJ = Proj<(H >> 1), (H & 1) ? 1 : -1>;
+  double2 h0[3], h1[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    h0[c] = cadd(cvt(raw[c]), ph<PJ::P0>(cvt(raw[PJ::A0 * 3 + c])));
+    h1[c] = cadd(cvt(raw[3 + c]), ph<PJ::P1>(cvt(raw[PJ::A1 * 3 + c])));
+  }
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    hs[a][lane] = u0[a];
-    hs[3 + a][lane] = u1[a];
+    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      s0 = cadd(s0, cmul(u[a][b], h0[b]));
+      s1 = cadd(s1, cmul(u[a][b], h1[b]));
+    }
+    hs[a][lane] = cscale(s0, fac);
+    hs[3 + a][lane] = cscale(s1, fac);
   }
 }
 
@@ -94,12 +116,13 @@ __device__ inline void load_hop_link(double2 (&u)[3][3], const T* U, int V, int 
 template <typename T>
 __global__ __launch_bounds__(kBStencilThreads) void k_bstencil(const BGroup* __restrict__ groups,
                                                                const BSys* __restrict__ sys,
-                                                               const int* __restrict__ act, int j) {
+                                                               const int* __restrict__ act, int j,
+                                                               int rhs) {
   const BGroup& G = groups[blockIdx.z];
   const StencilGeom& g = G.g;
   const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
   const int s = blockIdx.x * kSites + lane;
-  if (blockIdx.x * kSites >= g.V || (int)blockIdx.y * kRhsPerBlock >= G.nsys) return;
+  if (blockIdx.x * kSites >= g.V || (int)blockIdx.y * rhs >= G.nsys) return;
   const bool act_site = s < g.V;
   __shared__ double2 hs[8][6][64];
   // neighbour, hop factor and this wave's link, once for all right-hand sides
@@ -129,59 +152,74 @@ __global__ __launch_bounds__(kBStencilThreads) void k_bstencil(const BGroup* __r
       default: load_hop_link<7>(u, U, g.V, ulink); break;
     }
   }
-  const int rend = min(G.nsys, (int)(blockIdx.y + 1) * kRhsPerBlock);
-  for (int rr = blockIdx.y * kRhsPerBlock; rr < rend; ++rr) {
+  // Right-hand sides of this block in turn; the neighbour components (hop
+  // waves) and the diagonal (combining waves) of the next one are loaded
+  // while the current one is combined.
+  const int rbeg = blockIdx.y * rhs;
+  const int rend = min(G.nsys, rbeg + rhs);
+  T rc[12], rn[12], dc[4], dn[4];
+  auto prefetch = [&](int r, T (&raw)[12], T (&dia)[4]) {
+    // slot j exists for this system (its basis has k + 1 slots)
+    if (!act_site || r >= rend || j >= sys[G.sys[r]].k) return;
+    const T* in = basis<T>(sys[G.sys[r]]) + (int64_t)j * sys[G.sys[r]].n;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) raw[c] = in[c * g.V + nb];
+    if (h < 3)
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) dia[sp] = in[(sp * 3 + h) * g.V + s];
+  };
+  prefetch(rbeg, rc, dc);
+  for (int rr = rbeg; rr < rend; ++rr) {
     const int z = G.sys[rr];
     const BSys& S = sys[z];
-    if (j >= S.k || !live(S, act, z)) continue;   // uniform over the block
-    const T* in = basis<T>(S) + (int64_t)j * S.n;
-    T* out = basis<T>(S) + (int64_t)(j + 1) * S.n;
-    if (act_site) {
-      switch (h) {
-        case 0: bhop<0>(hs[0], in, u, g.V, nb, fac, lane); break;
-        case 1: bhop<1>(hs[1], in, u, g.V, nb, fac, lane); break;
-        case 2: bhop<2>(hs[2], in, u, g.V, nb, fac, lane); break;
-        case 3: bhop<3>(hs[3], in, u, g.V, nb, fac, lane); break;
-        case 4: bhop<4>(hs[4], in, u, g.V, nb, fac, lane); break;
-        case 5: bhop<5>(hs[5], in, u, g.V, nb, fac, lane); break;
-        case 6: bhop<6>(hs[6], in, u, g.V, nb, fac, lane); break;
-        default: bhop<7>(hs[7], in, u, g.V, nb, fac, lane); break;
+    const bool on = j < S.k && live(S, act, z);   // uniform over the block
+    prefetch(rr + 1, rn, dn);
+    if (on) {
+      T* out = basis<T>(S) + (int64_t)(j + 1) * S.n;
+      if (act_site) {
+        switch (h) {
+          case 0: bhop<0>(hs[0], rc, u, fac, lane); break;
+          case 1: bhop<1>(hs[1], rc, u, fac, lane); break;
+          case 2: bhop<2>(hs[2], rc, u, fac, lane); break;
+          case 3: bhop<3>(hs[3], rc, u, fac, lane); break;
+          case 4: bhop<4>(hs[4], rc, u, fac, lane); break;
+          case 5: bhop<5>(hs[5], rc, u, fac, lane); break;
+          case 6: bhop<6>(hs[6], rc, u, fac, lane); break;
+          default: bhop<7>(hs[7], rc, u, fac, lane); break;
+        }
       }
-    }
-    __syncthreads();
-    if (h < 3 && act_site) {
-      const int a = h;
-      double2 acc[4];
+      __syncthreads();
+      if (h < 3 && act_site) {
+        const int a = h;
+        double2 acc[4];
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) acc[sp] = make_double2(0.0, 0.0);
-      add_hop<0>(acc, hs[0], a, lane);
-      add_hop<1>(acc, hs[1], a, lane);
-      add_hop<2>(acc, hs[2], a, lane);
-      add_hop<3>(acc, hs[3], a, lane);
-      add_hop<4>(acc, hs[4], a, lane);
-      add_hop<5>(acc, hs[5], a, lane);
-      add_hop<6>(acc, hs[6], a, lane);
-      add_hop<7>(acc, hs[7], a, lane);
+        for (int sp = 0; sp < 4; ++sp) acc[sp] = make_double2(0.0, 0.0);
+        add_hop<0>(acc, hs[0], a, lane);
+        add_hop<1>(acc, hs[1], a, lane);
+        add_hop<2>(acc, hs[2], a, lane);
+        add_hop<3>(acc, hs[3], a, lane);
+        add_hop<4>(acc, hs[4], a, lane);
+        add_hop<5>(acc, hs[5], a, lane);
+        add_hop<6>(acc, hs[6], a, lane);
+        add_hop<7>(acc, hs[7], a, lane);
 #pragma unroll
-      for (int sp = 0; sp < 4; ++sp) {
-        const int c = sp * 3 + a;
-        double2 v = cadd(ld(in + c * g.V + s), acc[sp]);
-        if (sp >= 2) v = make_double2(-v.x, -v.y);   // gamma5
-        st(out + c * g.V + s, v);
+        for (int sp = 0; sp < 4; ++sp) {
+          const int c = sp * 3 + a;
+          double2 v = cadd(cvt(dc[sp]), acc[sp]);
+          if (sp >= 2) v = make_double2(-v.x, -v.y);   // gamma5
+          st(out + c * g.V + s, v);
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rc[c] = rn[c];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) dc[sp] = dn[sp];
   }
 }
 
 // ---- Gram-Schmidt (delayed reorthogonalisation) for every live system
-// Row blocking of the batched Gram-Schmidt kernels, chosen by the tuner:
-// rpt rows per thread in the dot kernel (hence row blocks of partial sums),
-// urt rows per thread in the update kernel.
-struct BTile {
-  int rpt;
-  int urt;
-};
 // row blocks of rpt row packs of `pack` rows per thread
 __host__ __device__ inline int brow_blocks(int64_t n, int rpt, int pack = 1) {
   const int64_t rb = (int64_t)kBNT * rpt * pack;
@@ -338,9 +376,12 @@ __global__ __launch_bounds__(kBNT) void k_bpdot(const BSys* __restrict__ sys, co
     const int64_t r = base + (int64_t)q * kBNT;
     if (r >= S.n) break;
     const double2 v = from_b ? S.b[r] : ld(basis<T>(S) + (int64_t)S.k * S.n + r);
+    double2 lv[8];   // all loads in flight before any is used
+#pragma unroll
+    for (int c = 0; c < 8; ++c) lv[c] = S.L[(int64_t)(i0 + min(c, cnt - 1)) * S.n + r];
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-      if (c < cnt) acc[c] = cadd(acc[c], cconjmul(S.L[(int64_t)(i0 + c) * S.n + r], v));
+      if (c < cnt) acc[c] = cadd(acc[c], cconjmul(lv[c], v));
   }
   __shared__ double2 red[kBNT / 64][8];
 #pragma unroll
@@ -558,6 +599,15 @@ int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
   return SK_OK;
 }
 
+template <typename T>
+int enqueue_bstencil(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
+  const int maxtiles = (int)((P.nmax / 12 + kSites - 1) / kSites);
+  hipLaunchKernelGGL((k_bstencil<T>), dim3(maxtiles, (P.maxrhs + tile.rhs - 1) / tile.rhs, P.ngroups),
+                     dim3(kBStencilThreads), 0, s, P.dgroups, P.dsys, P.act, j, tile.rhs);
+  SK_LAUNCH(hipGetLastError());
+  return SK_OK;
+}
+
 // One non-final Gram-Schmidt step for the tuner.
 template <typename T>
 int enqueue_bgs_step(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
@@ -584,10 +634,7 @@ int enqueue_bcycle(const BatchPlan& P, const BTile& tile, hipStream_t s) {
   const unsigned maxrows = (unsigned)((P.nmax + kBNT - 1) / kBNT);
   for (int j = 0; j <= P.kmax; ++j) {
     if (j < P.kmax) {
-      hipLaunchKernelGGL((k_bstencil<T>), dim3(maxtiles, (P.maxrhs + kRhsPerBlock - 1) / kRhsPerBlock,
-                                               P.ngroups),
-                         dim3(kBStencilThreads), 0, s, P.dgroups, P.dsys, P.act, j);
-      SK_LAUNCH(hipGetLastError());
+      SK_TRY(enqueue_bstencil<T>(P, tile, j, s));
     }
     SK_TRY(enqueue_bgs<T>(P, tile, j, s));
   }
@@ -621,8 +668,8 @@ int enqueue_bcycle_kind(int kind, const BatchPlan& P, const BTile& tile, hipStre
 // life of the process.
 std::mutex g_tune_mu;
 std::map<std::vector<int64_t>, BTile> g_tune_cache;
-thread_local BTile g_last_tile = {0, 0};
-std::atomic<int> g_force_rpt{0}, g_force_urt{0};   // 0: use the tuner
+thread_local BTile g_last_tile = {0, 0, 0};
+std::atomic<int> g_force_rpt{0}, g_force_urt{0}, g_force_rhs{4};   // rpt 0: use the tuner
 
 std::vector<int64_t> tune_key(const BatchPlan& P, const std::vector<BSys>& hs) {
   std::vector<int64_t> key = {P.mixed ? 1 : 0, P.nsys};
@@ -636,7 +683,8 @@ std::vector<int64_t> tune_key(const BatchPlan& P, const std::vector<BSys>& hs) {
 template <typename T>
 int tune_tiles(const BatchPlan& P, hipStream_t s, BTile* best) {
   const int j = P.kmin / 2;
-  static const BTile cand[] = {{1, 1}, {2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}, {4, 4}, {8, 4}};
+  static const BTile cand[] = {{1, 1, 4}, {2, 1, 4}, {4, 1, 4}, {8, 1, 4}, {2, 2, 4},
+                               {4, 2, 4}, {8, 2, 4}, {4, 4, 4}, {8, 4, 4}};
   const dim3 fill_grid((unsigned)brow_blocks(P.nmax, 1), 1, P.nsys);
   hipEvent_t e0, e1;
   SK_HIP(hipEventCreate(&e0));
@@ -666,6 +714,29 @@ int tune_tiles(const BatchPlan& P, hipStream_t s, BTile* best) {
     if (tt < tbest) {
       tbest = tt;
       *best = t;
+    }
+  }
+  // right-hand sides per stencil block, timed on the same data
+  if (rc == SK_OK) {
+    float sbest = 1e30f;
+    BTile t = *best;
+    for (int rhs : {1, 2, 4, 8}) {
+      t.rhs = rhs;
+      float tt = 0.0f;
+      for (int rep = 0; rep < 3 && rc == SK_OK; ++rep) {
+        if (hipEventRecord(e0, s) != hipSuccess) rc = SK_ERR_HIP;
+        if (rc == SK_OK) rc = enqueue_bstencil<T>(P, t, j, s);
+        if (rc == SK_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+          rc = SK_ERR_HIP;
+        float ms = 0.0f;
+        if (rc == SK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = SK_ERR_HIP;
+        if (rep > 0) tt += ms;
+      }
+      if (rc != SK_OK) break;
+      if (tt < sbest) {
+        sbest = tt;
+        best->rhs = rhs;
+      }
     }
   }
   hipEventDestroy(e0);
@@ -708,20 +779,23 @@ size_t sign_apply_batched_workspace_bytes(int nsys, const sk_batch_system* sys, 
   return carve_batch(c, nsys, sys, p, nullptr, nullptr, nullptr);
 }
 
-int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update) {
-  const bool off = rows_per_thread_dot == 0 && rows_per_thread_update == 0;
+int sk_batched_set_tile(int rows_per_thread_dot, int rows_per_thread_update, int rhs_per_block) {
+  const bool off = rows_per_thread_dot == 0 && rows_per_thread_update == 0 && rhs_per_block == 0;
   SK_CHECK(off || (rows_per_thread_dot >= 1 && rows_per_thread_dot <= 8 && rows_per_thread_update >= 1 &&
-                   rows_per_thread_update <= 8),
-           "rows per thread must be 1..8 (or both 0 for the tuner)");
+                   rows_per_thread_update <= 8 && rhs_per_block >= 1 && rhs_per_block <= kMaxGroupRhs),
+           "rows per thread must be 1..8 and right-hand sides per block 1..%d (or all 0 for the tuner)",
+           kMaxGroupRhs);
   g_force_urt.store(rows_per_thread_update);
+  g_force_rhs.store(off ? 4 : rhs_per_block);
   g_force_rpt.store(rows_per_thread_dot);
   return SK_OK;
 }
 
-int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update) {
-  SK_CHECK(rows_per_thread_dot && rows_per_thread_update, "NULL argument");
+int sk_batched_last_tile(int* rows_per_thread_dot, int* rows_per_thread_update, int* rhs_per_block) {
+  SK_CHECK(rows_per_thread_dot && rows_per_thread_update && rhs_per_block, "NULL argument");
   *rows_per_thread_dot = g_last_tile.rpt;
   *rows_per_thread_update = g_last_tile.urt;
+  *rhs_per_block = g_last_tile.rhs;
   return SK_OK;
 }
 
@@ -790,9 +864,9 @@ int sign_apply_batched(int nsys, const sk_batch_system* d, const sk_sign_params*
   SK_HIP(hipMemcpyAsync(P.poles, ptab.data(), ptab.size() * sizeof(double2), hipMemcpyHostToDevice, s));
   std::vector<int> act(nsys, 1);
   SK_HIP(hipMemcpyAsync(P.act, act.data(), nsys * sizeof(int), hipMemcpyHostToDevice, s));
-  BTile tile = {gs_rpt(P.nmax), 1};
+  BTile tile = {gs_rpt(P.nmax), 1, 4};
   if (g_force_rpt.load() > 0) {
-    tile = {g_force_rpt.load(), g_force_urt.load()};
+    tile = {g_force_rpt.load(), g_force_urt.load(), g_force_rhs.load()};
   } else {
     const std::vector<int64_t> key = tune_key(P, hs);
     bool have = false;

@@ -26,6 +26,8 @@
 // every reduction is finished by the next launch in a fixed order.
 #include "dcgs2_dev.h"
 
+#include <hip/hip_ext.h>
+
 namespace sk {
 
 namespace {
@@ -65,32 +67,49 @@ __global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ld
 // kGsGroups rows stored right after them (part + nrb * (2 j + 2)).
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
-                  const int* skip, hipStream_t s) {
+                  const int* skip, hipStream_t s, hipEvent_t t0, hipEvent_t t1, hipEvent_t r0,
+                  hipEvent_t r1) {
   const int nrb = gs_row_blocks(n, Pk<T>::P);
+  const bool red = gs_reduced(nrb);
   dim3 grid(nrb, j > 0 ? (j + kVC - 1) / kVC : 1);
-  hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
-                     part, skip);
+  if (t0 || t1)
+    hipExtLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, has_z ? 1 : 0, n,
+                          gs_rpt(n), part, skip);
+  else
+    hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
+                       part, skip);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !gs_reduced(nrb)) return e;
+  if (e != hipSuccess || !red) return e;
   const int pr = 2 * j + 2;
-  hipLaunchKernelGGL(k_dc_reduce, dim3((pr + 63) / 64, kGsGroups), dim3(kNT), 0, s, part, nrb, pr,
-                     part + (size_t)nrb * pr, skip);
+  if (r0 || r1)
+    hipExtLaunchKernelGGL(k_dc_reduce, dim3((pr + 63) / 64, kGsGroups), dim3(kNT), 0, s, r0, r1, 0, part,
+                          nrb, pr, part + (size_t)nrb * pr, skip);
+  else
+    hipLaunchKernelGGL(k_dc_reduce, dim3((pr + 63) / 64, kGsGroups), dim3(kNT), 0, s, part, nrb, pr,
+                       part + (size_t)nrb * pr, skip);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const double2* part,
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
-                     const int* skip, hipStream_t s) {
+                     const int* skip, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
   const int nrb = gs_row_blocks(n, Pk<T>::P);         // rows of partials (the dot kernel's grid)
   const int pr = 2 * j + 2;
   const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
   const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
   const int64_t rows_per_block = (int64_t)kNT * Pk<T>::P;   // one row pack per thread here
   const unsigned nb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
-  if (final_pass)
+  const bool ext = t0 || t1;
+  if (final_pass && ext)
+    hipExtLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, n, 1,
+                          src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
+  else if (final_pass)
     hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
+  else if (ext)
+    hipExtLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, n, 1,
+                          src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else
     hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
@@ -98,14 +117,16 @@ hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const
 }
 
 template hipError_t dc_dot<double2>(const double2*, int64_t, int, bool, int64_t, double2*,
-                                    const int*, hipStream_t);
+                                    const int*, hipStream_t, hipEvent_t, hipEvent_t, hipEvent_t,
+                                    hipEvent_t);
 template hipError_t dc_dot<float2>(const float2*, int64_t, int, bool, int64_t, double2*,
-                                   const int*, hipStream_t);
+                                   const int*, hipStream_t, hipEvent_t, hipEvent_t, hipEvent_t,
+                                   hipEvent_t);
 template hipError_t dc_update<double2>(double2*, int64_t, int, bool, int64_t, const double2*,
                                        const ArnoldiDev&, const double2*, double2*, bool,
-                                       const int*, hipStream_t);
+                                       const int*, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t dc_update<float2>(float2*, int64_t, int, bool, int64_t, const double2*,
                                       const ArnoldiDev&, const double2*, double2*, bool, const int*,
-                                      hipStream_t);
+                                      hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace sk

@@ -138,6 +138,28 @@ struct KTimer {
     int e1 = record();
     if (cur_e0 >= 0 && e1 >= 0) recs.push_back({cur_cls, cur_bytes, cur_e0, e1});
   }
+  // Kernel-stamped timing: two events that the launches themselves record
+  // at the start of the first and the end of the last kernel of the class
+  // (no event packets between kernels, so the interval is kernel time only,
+  // as a kernel trace reports it).  Both null when timing is off.
+  struct Ext {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+  };
+  int reserve() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+    return (int)used++;
+  }
+  Ext begin_ext(int cls, double bytes) {
+    if (!on()) return {};
+    const int a = reserve(), b = reserve();
+    if (a < 0 || b < 0) return {};
+    recs.push_back({cls, bytes, a, b});
+    return {pool[a], pool[b]};
+  }
   // call after the stream has been synchronised
   void flush() {
     if (!on()) return;
@@ -200,29 +222,28 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
     T* wj = w.W + (size_t)j * n;
     T* wj1 = w.W + (size_t)(j + 1) * n;
     // stencil: 12 in + 36 link + 12 out complex per site = 5 n complex
-    t.begin(SK_K_STENCIL, 5.0 * nn * c * power);
+    const auto es = t.begin_ext(SK_K_STENCIL, 5.0 * nn * c * power);
     if (power == 2) {
-      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, tmp, adjoint, nullptr, skip, s)));
-      SK_LAUNCH((launch_wilson<T, T, T>(op, U, tmp, wj1, adjoint, nullptr, skip, s)));
+      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, tmp, adjoint, nullptr, skip, s, es.t0, nullptr)));
+      SK_LAUNCH((launch_wilson<T, T, T>(op, U, tmp, wj1, adjoint, nullptr, skip, s, nullptr, es.t1)));
     } else {
-      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, wj1, adjoint, nullptr, skip, s)));
+      SK_LAUNCH((launch_wilson<T, T, T>(op, U, wj, wj1, adjoint, nullptr, skip, s, es.t0, es.t1)));
     }
-    t.end();
     // V_j^H [u, z]: j basis vectors + u + z read once
-    t.begin(SK_K_GS_DOT, (j + 2) * nn * c);
-    SK_LAUNCH((dc_dot<T>(w.W, n, j, true, n, w.gpart, skip, s)));
-    t.end();
+    const auto ed = t.begin_ext(SK_K_GS_DOT, (j + 2) * nn * c);
+    const int nrb = gs_row_blocks(n, sizeof(T) == 8 ? 2 : 1);
+    const auto er = gs_reduced(nrb) ? t.begin_ext(SK_K_GS_REDUCE, (nrb + kGsGroups) * (2.0 * j + 2) * 16.0)
+                                    : KTimer::Ext{};
+    SK_LAUNCH((dc_dot<T>(w.W, n, j, true, n, w.gpart, skip, s, ed.t0, ed.t1, er.t0, er.t1)));
     // v_j and u_{j+1} from one pass over V_j (+ read u, z; write v_j, u_{j+1})
-    t.begin(SK_K_GS_UPD_DOT, (j + 4) * nn * c);
+    const auto eu = t.begin_ext(SK_K_GS_UPD_DOT, (j + 4) * nn * c);
     SK_LAUNCH((dc_update<T>(w.W, n, j, false, n, w.gpart, a, sb(j - 1), sb(j), j == j0 && j0 > 0,
-                            skip, s)));
-    t.end();
+                            skip, s, eu.t0, eu.t1)));
   }
-  t.begin(SK_K_GS_UPD_NORM, (2 * k + 3) * nn * c);
-  SK_LAUNCH((dc_dot<T>(w.W, n, k, false, n, w.gpart, skip, s)));
+  const auto ef = t.begin_ext(SK_K_GS_UPD_NORM, (2 * k + 3) * nn * c);
+  SK_LAUNCH((dc_dot<T>(w.W, n, k, false, n, w.gpart, skip, s, ef.t0, nullptr)));
   SK_LAUNCH((dc_update<T>(w.W, n, k, true, n, w.gpart, a, sb(k - 1), sb(k), k == j0 && j0 > 0, skip,
-                          s)));
-  t.end();
+                          s, nullptr, ef.t1)));
   return SK_OK;
 }
 

@@ -90,20 +90,24 @@ __host__ __device__ inline size_t gs_part_entries(int nrb, int k) {
 
 // Arnoldi step kernels with delayed reorthogonalisation (dcgs2.hip).
 // Partials need gs_part_entries(gs_row_blocks(n), k) entries.
+// t0, t1 (optional): events stamped at the start of the first and the end
+// of the last kernel of the call (per-kernel timing).
+// dc_dot: (t0, t1) stamp the dot kernel, (r0, r1) the folding kernel if any.
 template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
-                  const int* skip, hipStream_t s);
+                  const int* skip, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr,
+                  hipEvent_t r0 = nullptr, hipEvent_t r1 = nullptr);
 template <typename T>
 hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const double2* part,
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
-                     const int* skip, hipStream_t s);
+                     const int* skip, hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // ------------------------------------------------------------ launchers
 // Stencil: out = alpha * H_W(+-mu) in; alpha = *in_scale (nullable = 1).
 template <typename TI, typename TL, typename TO>
 hipError_t launch_wilson(const sk_operator* op, const TL* links, const TI* in, TO* out,
                          int adjoint, const double* in_scale, const int* skip_flag,
-                         hipStream_t s);
+                         hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Residual form: out = b - (H_W - sigma) in, in double; `in` of type TI.
 template <typename TI>

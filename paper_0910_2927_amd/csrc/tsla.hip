@@ -235,12 +235,15 @@ __global__ __launch_bounds__(NT) void k_ts_dot(const TQ* __restrict__ Q, int64_t
   const double2 w = act ? ld(v + r) : zero2();
   const int pr = p + with_norm;
   double2* part = partial + (size_t)blockIdx.x * pr;
+  const int64_t rr = act ? r : 0;   // inactive lanes load a valid row and discard it
   for (int i0 = 0; i0 < p; i0 += CH) {
     double2 acc[CH];
     const int cnt = min(CH, p - i0);
+    TQ raw[CH];   // all loads of the chunk in flight before any is used
 #pragma unroll
-    for (int u = 0; u < CH; ++u)
-      acc[u] = (act && u < cnt) ? cconjmul(ld(Q + (int64_t)(i0 + u) * ldq + r), w) : zero2();
+    for (int u = 0; u < CH; ++u) raw[u] = Q[(int64_t)(i0 + min(u, cnt - 1)) * ldq + rr];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) acc[u] = (act && u < cnt) ? cconjmul(cvt(raw[u]), w) : zero2();
     block_reduce_store(acc, cnt, lds, part + i0);
   }
   if (with_norm) {
@@ -269,18 +272,15 @@ __global__ __launch_bounds__(NT) void k_ts_update(const TQ* __restrict__ Q, int6
   if (act) {
     const double al = a ? *a : 1.0;
     w = cscale(ld(in + r), al);
-    int i = 0;
-    for (; i + 4 <= p; i += 4) {
-      double2 q0 = ld(Q + (int64_t)(i + 0) * ldq + r);
-      double2 q1 = ld(Q + (int64_t)(i + 1) * ldq + r);
-      double2 q2 = ld(Q + (int64_t)(i + 2) * ldq + r);
-      double2 q3 = ld(Q + (int64_t)(i + 3) * ldq + r);
-      w = csub(w, cmul(q0, c[i + 0]));
-      w = csub(w, cmul(q1, c[i + 1]));
-      w = csub(w, cmul(q2, c[i + 2]));
-      w = csub(w, cmul(q3, c[i + 3]));
+    constexpr int B = 8;   // loads in flight per thread
+    for (int i = 0; i < p; i += B) {
+      TQ raw[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) raw[u] = Q[(int64_t)min(i + u, p - 1) * ldq + r];
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (i + u < p) w = csub(w, cmul(cvt(raw[u]), c[i + u]));
     }
-    for (; i < p; ++i) w = csub(w, cmul(ld(Q + (int64_t)i * ldq + r), c[i]));
     st(out + r, w);
     // the stored (possibly rounded) value is what later passes see
     w = ld(out + r);
@@ -291,12 +291,15 @@ __global__ __launch_bounds__(NT) void k_ts_update(const TQ* __restrict__ Q, int6
   if (red == 1) {
     pr = p;
     part = partial + (size_t)blockIdx.x * pr;
+    const int64_t rr = act ? r : 0;
     for (int i0 = 0; i0 < p; i0 += CH) {
       double2 acc[CH];
       const int cnt = min(CH, p - i0);
+      TQ raw[CH];
 #pragma unroll
-      for (int u = 0; u < CH; ++u)
-        acc[u] = (act && u < cnt) ? cconjmul(ld(Q + (int64_t)(i0 + u) * ldq + r), w) : zero2();
+      for (int u = 0; u < CH; ++u) raw[u] = Q[(int64_t)(i0 + min(u, cnt - 1)) * ldq + rr];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) acc[u] = (act && u < cnt) ? cconjmul(cvt(raw[u]), w) : zero2();
       block_reduce_store(acc, cnt, lds, part + i0);
     }
   } else {
@@ -325,7 +328,15 @@ __global__ __launch_bounds__(NT) void k_ts_gemv(const TQ* __restrict__ Q, int64_
   double2 acc0 = zero2();
   if (act) {
     double2 s = accumulate ? y[r] : zero2();
-    for (int i = 0; i < p; ++i) s = cadd(s, cmul(ld(Q + (int64_t)i * ldq + r), c[i]));
+    constexpr int B = 8;   // loads in flight per thread
+    for (int i = 0; i < p; i += B) {
+      TQ raw[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) raw[u] = Q[(int64_t)min(i + u, p - 1) * ldq + r];
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (i + u < p) s = cadd(s, cmul(cvt(raw[u]), c[i + u]));
+    }
     y[r] = s;
     acc0 = make_double2(cabs2(s), 0.0);
   }
@@ -348,11 +359,19 @@ __global__ __launch_bounds__(NT) void k_ts_multi_gemv(const TQ* __restrict__ Q, 
     double2 acc[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) acc[u] = zero2();
-    for (int j = 0; j < p; ++j) {
-      const double2 q = ld(Q + (int64_t)j * ldq + r);
+    constexpr int B = 4;   // basis loads in flight per thread
+    for (int j = 0; j < p; j += B) {
+      TQ raw[B];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (o0 + u < nout) acc[u] = cadd(acc[u], cmul(q, C[(size_t)(o0 + u) * ldc + j]));
+      for (int b = 0; b < B; ++b) raw[b] = Q[(int64_t)min(j + b, p - 1) * ldq + r];
+#pragma unroll
+      for (int b = 0; b < B; ++b) {
+        if (j + b >= p) break;
+        const double2 q = cvt(raw[b]);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (o0 + u < nout) acc[u] = cadd(acc[u], cmul(q, C[(size_t)(o0 + u) * ldc + j + b]));
+      }
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u)

@@ -16,6 +16,8 @@
 // neighbours through L2.
 #include "stencil_dev.h"
 
+#include <hip/hip_ext.h>
+
 #include <cstring>
 
 namespace sk {
@@ -123,10 +125,16 @@ static int stencil_blocks(int V) { return (V + kSitesPerBlock - 1) / kSitesPerBl
 
 template <typename TI, typename TL, typename TO>
 hipError_t launch_wilson(const sk_operator* op, const TL* links, const TI* in, TO* out, int adjoint,
-                         const double* in_scale, const int* skip, hipStream_t s) {
+                         const double* in_scale, const int* skip, hipStream_t s, hipEvent_t t0,
+                         hipEvent_t t1) {
   StencilGeom g = make_geom(op, adjoint);
-  hipLaunchKernelGGL((k_wilson<0, TI, TL, TO>), dim3(stencil_blocks(g.V)), dim3(kStencilThreads), 0, s,
-                     g, links, in, out, in_scale, skip, (const double2*)nullptr, make_double2(0.0, 0.0));
+  if (t0 || t1)
+    hipExtLaunchKernelGGL((k_wilson<0, TI, TL, TO>), dim3(stencil_blocks(g.V)), dim3(kStencilThreads), 0,
+                          s, t0, t1, 0, g, links, in, out, in_scale, skip, (const double2*)nullptr,
+                          make_double2(0.0, 0.0));
+  else
+    hipLaunchKernelGGL((k_wilson<0, TI, TL, TO>), dim3(stencil_blocks(g.V)), dim3(kStencilThreads), 0, s,
+                       g, links, in, out, in_scale, skip, (const double2*)nullptr, make_double2(0.0, 0.0));
   return hipGetLastError();
 }
 
@@ -142,10 +150,12 @@ hipError_t launch_wilson_residual(const sk_operator* op, const double2* links, c
 
 template hipError_t launch_wilson<double2, double2, double2>(const sk_operator*, const double2*,
                                                              const double2*, double2*, int,
-                                                             const double*, const int*, hipStream_t);
+                                                             const double*, const int*, hipStream_t,
+                                                             hipEvent_t, hipEvent_t);
 template hipError_t launch_wilson<float2, float2, float2>(const sk_operator*, const float2*,
                                                           const float2*, float2*, int,
-                                                          const double*, const int*, hipStream_t);
+                                                          const double*, const int*, hipStream_t,
+                                                          hipEvent_t, hipEvent_t);
 template hipError_t launch_wilson_residual<double2>(const sk_operator*, const double2*,
                                                     const double2*, const double2*, double2,
                                                     double2*, hipStream_t);

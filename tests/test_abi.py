@@ -109,11 +109,13 @@ def test_batched_entry_point_host_errors():
 def test_batched_tile_override_validation():
     from paper_0910_2927_amd import _lib
     lib = _lib.load()
-    assert lib.sk_batched_set_tile(0, 0) == _lib.SK_OK
-    assert lib.sk_batched_set_tile(9, 1) == _lib.SK_ERR_ARG
-    assert lib.sk_batched_set_tile(2, 0) == _lib.SK_ERR_ARG
-    assert lib.sk_batched_set_tile(4, 2) == _lib.SK_OK
-    assert lib.sk_batched_set_tile(0, 0) == _lib.SK_OK
-    a, b = C.c_int(-1), C.c_int(-1)
-    assert lib.sk_batched_last_tile(C.byref(a), C.byref(b)) == _lib.SK_OK
-    assert lib.sk_batched_last_tile(None, None) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(0, 0, 0) == _lib.SK_OK
+    assert lib.sk_batched_set_tile(9, 1, 4) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(2, 0, 4) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(2, 1, 0) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(2, 1, 65) == _lib.SK_ERR_ARG
+    assert lib.sk_batched_set_tile(4, 2, 8) == _lib.SK_OK
+    assert lib.sk_batched_set_tile(0, 0, 0) == _lib.SK_OK
+    a, b, c = C.c_int(-1), C.c_int(-1), C.c_int(-1)
+    assert lib.sk_batched_last_tile(C.byref(a), C.byref(b), C.byref(c)) == _lib.SK_OK
+    assert lib.sk_batched_last_tile(None, None, None) == _lib.SK_ERR_ARG

@@ -237,23 +237,24 @@ def test_row_blocking_does_not_change_results():
     srcs = [to_dev(si.z2_source(12 * V, 500 + i), V) for i in range(6)]
     outs = {}
     try:
-        for tile in [(1, 1), (2, 1), (8, 1), (4, 2), (8, 4), (0, 0)]:
+        for tile in [(1, 1, 1), (2, 1, 4), (8, 1, 2), (4, 2, 8), (8, 4, 3), (0, 0, 0)]:
             assert lib.sk_batched_set_tile(*tile) == _lib.SK_OK
             announce(f"sign_apply_batched 6^4 x6 tile {tile}")
             solver = api.BatchedSignSolver([(op, None)] * 6, sig, om, 24, tol=1e-10, max_cycles=300)
             res = solver(srcs)
             assert all(r.converged for r in res)
             outs[tile] = [r.x.clone() for r in res]
-            if tile == (0, 0):
+            if tile == (0, 0, 0):
                 print("tuner picked", solver.tile)
                 assert solver.tile["dot_rows_per_thread"] in (1, 2, 4, 8)
                 assert solver.tile["update_rows_per_thread"] in (1, 2, 4)
+                assert solver.tile["rhs_per_stencil_block"] in (1, 2, 4, 8)
             else:
-                assert solver.tile == {"dot_rows_per_thread": tile[0],
-                                       "update_rows_per_thread": tile[1]}
+                assert solver.tile == {"dot_rows_per_thread": tile[0], "update_rows_per_thread": tile[1],
+                                       "rhs_per_stencil_block": tile[2]}
     finally:
-        lib.sk_batched_set_tile(0, 0)
-    ref = outs[(1, 1)]
+        lib.sk_batched_set_tile(0, 0, 0)
+    ref = outs[(1, 1, 1)]
     for tile, xs in outs.items():
         for a, b in zip(xs, ref):
             d = rel(from_dev(a, V), from_dev(b, V))
