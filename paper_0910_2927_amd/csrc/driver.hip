@@ -404,7 +404,6 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   const int64_t n = ca.n;
   const int k = ca.p->k, m = ca.p->m, N = ca.ps->n;
   const ArnoldiDev a = arn_of(w, k);
-  const int cs = ts_counter_stride(n);
   const int* skip = &w.st->breakdown;
   KTimer& tm = *ca.tm;
   const double cb = (double)sizeof(T), nn = (double)n;
@@ -414,36 +413,21 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   tm.begin(SK_K_SMALL, 0.0);
   SK_LAUNCH(launch_fom_small(a, k, *ca.ps, w.rho, w.Y, w.U, w.ucoef, ca.X ? w.ycoef : nullptr, ca.s));
   tm.end();
-  TsEpiArgs ex = epi_of(EPI_XNORM, a);
-  ex.dst_scalar = &w.st->xnorm2;
   tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * nn * 16.0);
-  SK_LAUNCH((ts_gemv<T>(w.W, n, k, w.ucoef, ca.x, n, true, 2, ex, w.partial, w.counter + 6 * cs,
-                        &w.st->kdone, nullptr, ca.s)));
+  SK_LAUNCH((cycle_x_update<T>(w.W, n, w.ucoef, &w.st->kdone, ca.x, (double*)w.partial, w.st, ca.s)));
   tm.end();
   if (ca.X) {
     tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * N * nn * 16.0);
     SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, ca.X, n, &w.st->kdone, ca.s)));
     tm.end();
   }
-  // r = v_{k+1};  r = (I - P) r  (projection step)
-  T* Wk = w.W + (size_t)k * n;
-  TsEpiArgs eb = epi_of(EPI_BETA, a);
-  eb.dst_scalar = &w.st->beta;
-  eb.dst_scale = w.scale + k + 1;   // unused slot: every stored v_j has unit norm
-  if (m > 0) {
-    TsEpiArgs ed = epi_of(EPI_DEFL, a);
-    ed.out = w.dc;
-    ed.alpha = w.scale + k;
-    ed.dst_scalar = &w.st->leak;
-    tm.begin(SK_K_PROJECT, m * nn * 16.0 + nn * cb);
-    SK_LAUNCH((ts_dot<double2, T>(Lv, n, m, Wk, n, false, ed, w.partial, w.counter + 7 * cs, skip, ca.s)));
-    tm.end();
-  }
+  // r = v_{k+1};  r = (I - P) r  (projection step); ||r|| is taken by the
+  // next cycle's first Gram-Schmidt step
+  const T* Wk = w.W + (size_t)k * n;
   const bool proj = m > 0 && ca.p->project_each_cycle;
-  tm.begin(SK_K_PROJECT, (proj ? m * nn * 16.0 : 0.0) + nn * cb + nn * (double)sizeof(TN));
-  SK_LAUNCH((ts_update<double2, T, TN>(proj ? R : (const double2*)nullptr, n, proj ? m : 0, w.dc,
-                                       w.scale + k, Wk, wn.W, n, 2, eb, w.partial, w.counter + 8 * cs,
-                                       skip, ca.s)));
+  tm.begin(SK_K_PROJECT, (m > 0 ? m * nn * 16.0 + nn * cb : 0.0) + (proj ? m * nn * 16.0 : 0.0) + nn * cb +
+                             nn * (double)sizeof(TN));
+  SK_LAUNCH((cycle_restart<T, TN>(R, Lv, m, proj, Wk, wn.W, n, w.partial, w.st, skip, ca.s)));
   tm.end();
   return SK_OK;
 }
@@ -585,7 +569,7 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   CycleGraphs graphs;
   const bool use_graph = !tm.on();   // per-kernel timing needs plain launches
   int small = 0, status = SK_ERR_NOCONV;
-  double beta_cycle = hs.beta, first_upd = 0.0;
+  double first_upd = 0.0;
   bool diverged = false;
   for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
     // the next cycle's precision is decided before this one is enqueued:
@@ -605,11 +589,10 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
       stats->x_norm = std::sqrt(hs.xnorm2);
       if (cyc < stats->hist_cap) {
         if (stats->hist_update) stats->hist_update[cyc] = hs.upd_norm;
-        if (stats->hist_beta) stats->hist_beta[cyc] = beta_cycle;
+        if (stats->hist_beta) stats->hist_beta[cyc] = hs.beta;   // ||r|| at the cycle's start
         if (stats->hist_leak) stats->hist_leak[cyc] = hs.leak;
       }
     }
-    beta_cycle = hs.beta;
     if (hs.nonfinite) {
       set_error("non-finite value in cycle %d (restarted FOM diverged or bad input)", cyc + 1);
       status = SK_ERR_NAN;

@@ -163,6 +163,19 @@ hipError_t launch_fom_small(const ArnoldiDev& arn, int k, const PoleSet& poles,
                             double2* rho, double2* Y, double2* U, double2* ucoef,
                             double2* ycoef, hipStream_t s);
 
+// End of a restart cycle without fences (cycle.hip): x += V_kk u and
+// st->xnorm2 (xpart: cycle_xpart_entries(n) doubles), and the restart
+// vector out = (I - R L^H) v (project) or v, with st->leak = ||L^H v||
+// (dpart: cycle_dpart_rows(n) x m complex).
+int cycle_xpart_entries(int64_t n);
+int cycle_dpart_rows(int64_t n);
+template <typename T>
+hipError_t cycle_x_update(const T* W, int64_t n, const double2* ucoef, const int* kdone, double2* x,
+                          double* xpart, CycleState* st, hipStream_t s);
+template <typename T, typename TN>
+hipError_t cycle_restart(const double2* R, const double2* L, int m, bool project, const T* v, TN* out,
+                         int64_t n, double2* dpart, CycleState* st, const int* skip, hipStream_t s);
+
 // Link and mu gradient of Re<eta, g(H) b> from per-shift solutions (backward.hip).
 int grad_blocks(int64_t V);
 hipError_t launch_grad(const sk_operator* op, const PoleSet& ps, const double2* X, const double2* Z,

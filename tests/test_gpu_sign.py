@@ -196,3 +196,32 @@ def test_graph_replay_matches_plain_launches():
         assert bool((x1 == x2).all())
         if prec == "mixed":
             assert 0 < r1.cycles_c64 < r1.cycles
+
+
+def test_projection_step_keeps_the_deflated_part_out():
+    """Sect. 4/5: without the projection step after every cycle the
+    deflated directions leak back into the restart vector (||L^H r|| grows
+    cycle by cycle); with it the leak stays at rounding level and the
+    result matches the oracle's x*."""
+    from paper_0910_2927_amd import api
+    import torch
+    dims = (3, 4, 5, 6)
+    V, U, b, A = _problem(dims, 0.6, 0.3, 95, 96)
+    R, L, lam, F = deflation.lr_dense(A, 24)
+    sig, om = rational.kl_first_order(8, 1.5)
+    op = make_op(U, dims, 0.25, 0.3)
+    kw = dict(tol=1e-11, max_cycles=400, R=vecs_to_dev(R, V), Lv=vecs_to_dev(L, V),
+              F=torch.from_numpy(F).to(torch_dev()))
+    ref = xstar.xstar_dense(A, b, sig, om, R, L, F)
+    announce("sign_apply with and without the projection step")
+    on = api.sign_apply(op, to_dev(b, V), sig, om, 20, project_each_cycle=True, **kw)
+    off = api.sign_apply(op, to_dev(b, V), sig, om, 20, project_each_cycle=False, raise_on_error=False,
+                         **kw)
+    err_on = rel(from_dev(on.x, V), ref)
+    err_off = rel(from_dev(off.x, V), ref)
+    print(f"projection on: err {err_on:.2e}, max leak/beta {np.max(on.leaks / on.betas):.1e}; "
+          f"off: err {err_off:.2e}, leak/beta first {off.leaks[0] / off.betas[0]:.1e} "
+          f"last {off.leaks[-1] / off.betas[-1]:.1e}")
+    assert on.converged and err_on <= TOL_FP64
+    assert np.max(on.leaks / on.betas) < 1e-9
+    assert off.leaks[-1] / off.betas[-1] > 100 * np.max(on.leaks / on.betas)
