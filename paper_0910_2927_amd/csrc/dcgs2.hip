@@ -36,11 +36,11 @@ constexpr int kNT = kTsThreads;
 constexpr int kVC = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_dc_dot(const T* __restrict__ W, int64_t ldq, int j, int has_z,
-                                                int64_t n, int rpt, double2* __restrict__ part,
-                                                const int* skip) {
+__global__ __launch_bounds__(kSdThreads) void k_dc_dot(const T* __restrict__ W, int64_t ldq, int j,
+                                                       int has_z, int64_t n, int rpt,
+                                                       double2* __restrict__ part, const int* skip) {
   if (skip && *skip) return;
-  dc_dot_body<T>(W, ldq, j, has_z, n, rpt, part, blockIdx.x, blockIdx.y);
+  dc_dot_body<T, kSdThreads>(W, ldq, j, has_z, n, rpt, part, blockIdx.x, blockIdx.y);
 }
 
 __global__ __launch_bounds__(kNT) void k_dc_reduce(const double2* __restrict__ part, int nrb, int pr,
@@ -49,16 +49,21 @@ __global__ __launch_bounds__(kNT) void k_dc_reduce(const double2* __restrict__ p
   dc_reduce_body(part, nrb, pr, out, blockIdx.x, blockIdx.y);
 }
 
+// Update blocks of kSuThreads threads: the per-block prologue (folding the
+// partial sums, H_j t) is shared by more rows.
+constexpr int kSuThreads = 512;
+
 template <typename T, bool FINAL>
-__global__ __launch_bounds__(kNT) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
-                                                   int rpt, const double2* __restrict__ part, int nrb,
-                                                   ArnoldiDev arn, const double2* __restrict__ s_prev,
-                                                   double2* __restrict__ s_cur, int fresh,
-                                                   const int* skip) {
+__global__ __launch_bounds__(kSuThreads, 4) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
+                                                          int rpt, const double2* __restrict__ part,
+                                                          int nrb, ArnoldiDev arn,
+                                                          const double2* __restrict__ s_prev,
+                                                          double2* __restrict__ s_cur, int fresh,
+                                                          const int* skip) {
   if (skip && *skip) return;
   (void)rpt;
-  dc_update_body<T, FINAL>(W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
-                           (int64_t)blockIdx.x * kNT + threadIdx.x, 1, blockIdx.x == 0);
+  dc_update_body<T, FINAL, kSuThreads>(W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
+                                       (int64_t)blockIdx.x * kSuThreads + threadIdx.x, 1, blockIdx.x == 0);
 }
 
 }  // namespace
@@ -69,15 +74,16 @@ template <typename T>
 hipError_t dc_dot(const T* W, int64_t ldq, int j, bool has_z, int64_t n, double2* part,
                   const int* skip, hipStream_t s, hipEvent_t t0, hipEvent_t t1, hipEvent_t r0,
                   hipEvent_t r1) {
-  const int nrb = gs_row_blocks(n, Pk<T>::P);
+  const int nrb = sd_row_blocks(n, Pk<T>::P);
+  const int rpt = sd_rpt(n, Pk<T>::P);
   const bool red = gs_reduced(nrb);
   dim3 grid(nrb, j > 0 ? (j + kVC - 1) / kVC : 1);
   if (t0 || t1)
-    hipExtLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, has_z ? 1 : 0, n,
-                          gs_rpt(n), part, skip);
+    hipExtLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kSdThreads), 0, s, t0, t1, 0, W, ldq, j, has_z ? 1 : 0,
+                          n, rpt, part, skip);
   else
-    hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kNT), 0, s, W, ldq, j, has_z ? 1 : 0, n, gs_rpt(n),
-                       part, skip);
+    hipLaunchKernelGGL((k_dc_dot<T>), grid, dim3(kSdThreads), 0, s, W, ldq, j, has_z ? 1 : 0, n, rpt, part,
+                       skip);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !red) return e;
   const int pr = 2 * j + 2;
@@ -94,24 +100,24 @@ template <typename T>
 hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const double2* part,
                      const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
                      const int* skip, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
-  const int nrb = gs_row_blocks(n, Pk<T>::P);         // rows of partials (the dot kernel's grid)
+  const int nrb = sd_row_blocks(n, Pk<T>::P);         // rows of partials (the dot kernel's grid)
   const int pr = 2 * j + 2;
   const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
   const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
-  const int64_t rows_per_block = (int64_t)kNT * Pk<T>::P;   // one row pack per thread here
+  const int64_t rows_per_block = (int64_t)kSuThreads * Pk<T>::P;   // one row pack per thread here
   const unsigned nb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
   const bool ext = t0 || t1;
   if (final_pass && ext)
-    hipExtLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, n, 1,
+    hipExtLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kSuThreads), 0, s, t0, t1, 0, W, ldq, j, n, 1,
                           src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else if (final_pass)
-    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
+    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kSuThreads), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else if (ext)
-    hipExtLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, t0, t1, 0, W, ldq, j, n, 1,
+    hipExtLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kSuThreads), 0, s, t0, t1, 0, W, ldq, j, n, 1,
                           src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   else
-    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kNT), 0, s, W, ldq, j, n, 1, src, nrows,
+    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kSuThreads), 0, s, W, ldq, j, n, 1, src, nrows,
                        arn, s_prev, s_cur, fresh ? 1 : 0, skip);
   return hipGetLastError();
 }

@@ -41,8 +41,12 @@ template <> struct Pk<float2> {
   }
 };
 
+// Column sums of nrows x pr partials (row-major) into sums[0..pr), BT
+// threads, scratch of BT entries; fixed order.
+template <int BT = NT>
 __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, int pr, double2* sums,
                                    double2* scratch) {
+  constexpr int NW = BT / 64;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int i0 = 0; i0 < pr; i0 += 64) {
     const int i = i0 + lane;
@@ -74,7 +78,7 @@ __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, i
 // it is used, so a wave has VC + 2 loads in flight.  FULL: the chunk holds
 // VC vectors (no masking); otherwise vectors past cnt re-read a valid
 // vector and are masked out.  base, rpt count packs.
-template <typename T, bool HAS_Z, bool FULL>
+template <typename T, bool HAS_Z, bool FULL, int BT>
 __device__ inline void dot_rows(const T* __restrict__ W, int64_t ldq, int j, int i0, int cnt, int64_t n,
                                 int rpt, int64_t base, bool first, double2 (&at)[VC], double2 (&ap)[VC],
                                 double2& aa, double2& ag) {
@@ -88,7 +92,7 @@ __device__ inline void dot_rows(const T* __restrict__ W, int64_t ldq, int j, int
   for (int c = 0; c < VC; ++c)
     vb[c] = reinterpret_cast<const PT*>(W + (int64_t)(i0 + (FULL ? c : min(c, last))) * ldq);
   for (int q = 0; q < rpt; ++q) {
-    const int64_t rp = base + (int64_t)q * NT;
+    const int64_t rp = base + (int64_t)q * BT;
     if (rp * K::P >= n) break;
     PT raw[VC];
     const PT ru = u[rp];
@@ -118,24 +122,26 @@ __device__ inline void dot_rows(const T* __restrict__ W, int64_t ldq, int j, int
 // Partial sums of t = V_j^H u, p = V_j^H z (chunk of VC vectors) and, in
 // chunk 0, alpha = u^H u and gamma = u^H z.  Layout per row block:
 // [t_0..t_{j-1}, p_0..p_{j-1}, alpha, gamma].
-template <typename T>
+// BT: threads of the block (rows of a block: BT * rpt packs).
+template <typename T, int BT = NT>
 __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, int has_z,
                                    int64_t n, int rpt, double2* __restrict__ part, int rb, int ch) {
-  __shared__ double2 red[NW][2 * VC + 2];
+  constexpr int BW = BT / 64;
+  __shared__ double2 red[BW][2 * VC + 2];
   const int i0 = ch * VC;
   const int cnt = max(0, min(VC, j - i0));
   double2 at[VC], ap[VC];
   double2 aa = z2(), ag = z2();
 #pragma unroll
   for (int q = 0; q < VC; ++q) at[q] = ap[q] = z2();
-  const int64_t base = (int64_t)rb * NT * rpt + threadIdx.x;   // in packs
+  const int64_t base = (int64_t)rb * BT * rpt + threadIdx.x;   // in packs
   const bool first = ch == 0;
   if (has_z) {
-    if (cnt == VC) dot_rows<T, true, true>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
-    else dot_rows<T, true, false>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    if (cnt == VC) dot_rows<T, true, true, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    else dot_rows<T, true, false, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
   } else {
-    if (cnt == VC) dot_rows<T, false, true>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
-    else dot_rows<T, false, false>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    if (cnt == VC) dot_rows<T, false, true, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
+    else dot_rows<T, false, false, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
   }
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -164,7 +170,7 @@ __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, 
   if (t < 2 * VC + 2) {
     double2 s = red[0][t];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) s = cadd(s, red[w][t]);
+    for (int w = 1; w < BW; ++w) s = cadd(s, red[w][t]);
     if (t < VC) {
       if (t < cnt) dst[i0 + t] = s;
     } else if (t < 2 * VC) {
@@ -210,28 +216,29 @@ __device__ inline void dc_reduce_body(const double2* __restrict__ part, int nrb,
 // Second pass of u_j and (unless FINAL) first pass of the next vector.
 // `fresh`: first step after a thick restart of the eigensolver, where the
 // columns before j already hold the restarted Rayleigh quotient (kept as is).
-// The thread updates row packs r0, r0 + NT, ..., urt of them (the block's
-// reduction of the partial dots is shared by its NT * urt packs).
-template <typename T, bool FINAL>
+// The thread updates row packs r0, r0 + BT, ..., urt of them (the block's
+// reduction of the partial dots is shared by its BT * urt packs).
+template <typename T, bool FINAL, int BT = NT>
 __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int64_t n,
                                       const double2* __restrict__ part, int nrb,
                                       const ArnoldiDev& arn, const double2* __restrict__ s_prev,
                                       double2* __restrict__ s_cur, int fresh, int64_t r0,
                                       int urt, bool writer) {
+  constexpr int BW = BT / 64;
   __shared__ double2 sums[2 * kMaxK + 4];
-  __shared__ double2 scratch[NT];
+  __shared__ double2 scratch[BT];
   __shared__ double2 ct[kMaxK + 2];   // t
   __shared__ double2 ce[kMaxK + 2];   // e
   __shared__ double2 cs[kMaxK + 2];   // s_j
-  __shared__ double red[NW];
+  __shared__ double red[BW];
   __shared__ double sc[4];            // beta, d/beta (re, im), flag
   __shared__ double2 cd;
   const int pr = 2 * j + 2;
-  reduce_cols(part, nrb, pr, sums, scratch);
+  reduce_cols<BT>(part, nrb, pr, sums, scratch);
   const int tid = threadIdx.x;
   // |t|^2 and |s_{j-1}|^2
   double tt = 0.0, ss = 0.0;
-  for (int i = tid; i < j; i += NT) {
+  for (int i = tid; i < j; i += BT) {
     ct[i] = sums[i];
     tt += cabs2(sums[i]);
     if (!fresh) ss += cabs2(s_prev[i]);
@@ -242,7 +249,7 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   __syncthreads();
   if (tid == 0) {
     double a = 0.0;
-    for (int w = 0; w < NW; ++w) a += red[w];
+    for (int w = 0; w < BW; ++w) a += red[w];
     sc[1] = a;
   }
   __syncthreads();
@@ -250,7 +257,7 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   __syncthreads();
   if (tid == 0) {
     double sprev = 0.0;
-    for (int w = 0; w < NW; ++w) sprev += red[w];
+    for (int w = 0; w < BW; ++w) sprev += red[w];
     // ||A v_{j-1}||^2 = alpha + ||s_{j-1}||^2 sets the breakdown scale
     const double alpha = sums[2 * j].x;
     const double b2 = alpha - sc[1];
@@ -275,42 +282,56 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   __syncthreads();
   // final column j-1 = s_{j-1} + t (also on breakdown: K_j is invariant)
   if (writer && !fresh)
-    for (int i = tid; i < j; i += NT) arn.H[(size_t)(j - 1) * arn.ldh + i] = cadd(s_prev[i], ct[i]);
+    for (int i = tid; i < j; i += BT) arn.H[(size_t)(j - 1) * arn.ldh + i] = cadd(s_prev[i], ct[i]);
   if (sc[3] != 0.0) return;
   const double beta = sc[0], ib = 1.0 / beta;
   if (!FINAL) {
     // s_j from the reduced quantities; H_j t uses columns 0..j-2 of H and
     // the final column j-1 = s_{j-1} + t
     const double2 gamma = sums[2 * j + 1];
-    double2 tp = z2();
-    for (int i = tid; i < j; i += NT) {
-      // (H_j t)_i over columns l >= i-1 (Hessenberg); the last column is
-      // s_{j-1} + t unless the columns came from a thick restart
+    // (H_j t)_i over columns l >= i-1 (Hessenberg); the last column is
+    // s_{j-1} + t unless the columns came from a thick restart.  G = BW
+    // consecutive threads share an output i (strided partial sums, then a
+    // fixed-order combination over the group), so the loads of H are
+    // spread over the block instead of serialised in j threads.
+    constexpr int G = BW;
+    const int lend = (fresh ? j : j - 1);
+    for (int i0 = 0; i0 < j; i0 += BT / G) {
+      const int i = i0 + tid / G, g = tid % G;
       double2 ht = z2();
-      const int lend = (fresh ? j : j - 1);
-      int l = max(0, i - 1);
-      for (; l + 8 <= lend; l += 8) {
-        double2 hv[8];
+      if (i < j) {
+        int l = max(0, i - 1) + g;
+        for (; l + 3 * G < lend; l += 4 * G) {
+          double2 hv[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) hv[u] = arn.H[(size_t)(l + u) * arn.ldh + i];
+          for (int u = 0; u < 4; ++u) hv[u] = arn.H[(size_t)(l + u * G) * arn.ldh + i];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ht = cadd(ht, cmul(hv[u], ct[l + u]));
+          for (int u = 0; u < 4; ++u) ht = cadd(ht, cmul(hv[u], ct[l + u * G]));
+        }
+        for (; l < lend; l += G) ht = cadd(ht, cmul(arn.H[(size_t)l * arn.ldh + i], ct[l]));
       }
-      for (; l < lend; ++l) ht = cadd(ht, cmul(arn.H[(size_t)l * arn.ldh + i], ct[l]));
-      if (!fresh && j > 0) ht = cadd(ht, cmul(cadd(s_prev[i], ct[i]), ct[j - 1]));
-      const double2 si = cscale(csub(sums[j + i], ht), ib);     // (p_i - (H_j t)_i) / beta
-      cs[i] = si;
-      ce[i] = cadd(cscale(ht, ib), si);                         // c_i = (H_j t)_i / beta + s_i
-      tp = cadd(tp, cconjmul(ct[i], sums[j + i]));              // t^H p
+#pragma unroll
+      for (int off = 1; off < G; off <<= 1) {   // groups of G consecutive lanes (G divides 64)
+        ht.x += __shfl_xor(ht.x, off, 64);
+        ht.y += __shfl_xor(ht.y, off, 64);
+      }
+      if (g == 0 && i < j) {
+        if (!fresh && j > 0) ht = cadd(ht, cmul(cadd(s_prev[i], ct[i]), ct[j - 1]));
+        const double2 si = cscale(csub(sums[j + i], ht), ib);     // (p_i - (H_j t)_i) / beta
+        cs[i] = si;
+        ce[i] = cadd(cscale(ht, ib), si);                         // c_i = (H_j t)_i / beta + s_i
+      }
     }
+    double2 tp = z2();
+    for (int i = tid; i < j; i += BT) tp = cadd(tp, cconjmul(ct[i], sums[j + i]));   // t^H p
     tp.x = wave_sum(tp.x);
     tp.y = wave_sum(tp.y);
-    __shared__ double2 tpr[NW];
+    __shared__ double2 tpr[BW];
     if ((tid & 63) == 0) tpr[tid >> 6] = tp;
     __syncthreads();
     if (tid == 0) {
       double2 a = z2();
-      for (int w = 0; w < NW; ++w) a = cadd(a, tpr[w]);
+      for (int w = 0; w < BW; ++w) a = cadd(a, tpr[w]);
       // v_j^H A v_j = ((gamma - t^H p)/beta - beta t_{j-1}) / beta
       double2 vav = cscale(csub(gamma, a), ib);
       if (j > 0) vav = csub(vav, cscale(ct[j - 1], beta));
@@ -320,9 +341,9 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
       cd = cscale(d, ib);   // d / beta
     }
     __syncthreads();
-    for (int i = tid; i < j; i += NT) ce[i] = csub(ce[i], cmul(cd, ct[i]));   // e = c - (d/beta) t
+    for (int i = tid; i < j; i += BT) ce[i] = csub(ce[i], cmul(cd, ct[i]));   // e = c - (d/beta) t
     if (writer)
-      for (int i = tid; i <= j; i += NT) {
+      for (int i = tid; i <= j; i += BT) {
         s_cur[i] = cs[i];
         arn.H[(size_t)j * arn.ldh + i] = cs[i];   // provisional until step j+1
       }
@@ -333,7 +354,7 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   PT* u = reinterpret_cast<PT*>(W + (int64_t)j * ldq);
   PT* zv = reinterpret_cast<PT*>(W + (int64_t)(j + 1) * ldq);
   for (int q = 0; q < urt; ++q) {
-    const int64_t rp = r0 + (int64_t)q * NT;
+    const int64_t rp = r0 + (int64_t)q * BT;
     if (rp * K::P >= n) return;
     double2 at[K::P], ae[K::P];
 #pragma unroll

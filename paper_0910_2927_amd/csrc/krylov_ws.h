@@ -45,7 +45,7 @@ struct KrylovWs {
   double2* ycoef;
   double2* dc;
   double2* dc2;
-  double2* gpart;      // Gram-Schmidt partial dots, gs_part_entries(gs_row_blocks(n), k)
+  double2* gpart;      // Gram-Schmidt partial dots, gs_part_entries(sd_row_blocks(n), k)
   double2* sbuf;       // first-pass coefficients, 2 x (k+2) (alternating)
   size_t gpart_cap;    // entries of gpart
   int sbuf_k;          // k the first-pass buffers were sized for
@@ -55,7 +55,7 @@ struct KrylovWs {
 // workspace layout that runs enqueue_arnoldi).
 template <typename T>
 void carve_gs(Carver& c, KrylovWs<T>& w, int64_t n, int k) {
-  w.gpart_cap = gs_part_entries(gs_row_blocks(n), k);
+  w.gpart_cap = gs_part_entries(sd_row_blocks(n), k);
   w.gpart = c.template take<double2>(w.gpart_cap);
   w.sbuf = c.template take<double2>((size_t)2 * (k + 2));
   w.sbuf_k = k;
@@ -210,7 +210,7 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
   const int* skip = &w.st->breakdown;
   // every buffer the step kernels index must be there and large enough
   if (!w.W || !w.H || !w.st || !w.sbuf || !w.gpart || w.sbuf_k < k ||
-      w.gpart_cap < gs_part_entries(gs_row_blocks(n), k) || (power == 2 && !tmp)) {
+      w.gpart_cap < gs_part_entries(sd_row_blocks(n), k) || (power == 2 && !tmp)) {
     set_error("internal: Arnoldi workspace is missing a buffer or is too small");
     return SK_ERR_WORKSPACE;
   }
@@ -231,7 +231,7 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
     }
     // V_j^H [u, z]: j basis vectors + u + z read once
     const auto ed = t.begin_ext(SK_K_GS_DOT, (j + 2) * nn * c);
-    const int nrb = gs_row_blocks(n, sizeof(T) == 8 ? 2 : 1);
+    const int nrb = sd_row_blocks(n, sizeof(T) == 8 ? 2 : 1);
     const auto er = gs_reduced(nrb) ? t.begin_ext(SK_K_GS_REDUCE, (nrb + kGsGroups) * (2.0 * j + 2) * 16.0)
                                     : KTimer::Ext{};
     SK_LAUNCH((dc_dot<T>(w.W, n, j, true, n, w.gpart, skip, s, ed.t0, ed.t1, er.t0, er.t1)));

@@ -76,6 +76,24 @@ __host__ __device__ inline int gs_row_blocks(int64_t n, int pack = 1) {
   const int64_t rb = (int64_t)kTsThreads * gs_rpt(n) * pack;
   return (int)((n + rb - 1) / rb);
 }
+// The single-system dot kernel runs blocks of kSdThreads threads with
+// sd_rpt row packs per thread: as many as it takes for at most 32 row
+// blocks to cover the vector (no folding kernel) if that is <= 8; for
+// longer vectors enough for about 256 row blocks (then folded).
+constexpr int kSdThreads = 1024;
+__host__ __device__ inline int sd_rpt(int64_t n, int pack) {
+  const int64_t few = (int64_t)kSdThreads * pack * 32;
+  const int64_t r0 = (n + few - 1) / few;
+  if (r0 <= 8) return (int)(r0 < 1 ? 1 : r0);
+  const int64_t many = (int64_t)kSdThreads * pack * 256;
+  const int64_t r = (n + many - 1) / many;
+  return (int)(r < 1 ? 1 : (r > 8 ? 8 : r));
+}
+__host__ __device__ inline int sd_row_blocks(int64_t n, int pack = 1) {
+  const int64_t rb = (int64_t)kSdThreads * sd_rpt(n, pack) * pack;
+  return (int)((n + rb - 1) / rb);
+}
+
 // The dot kernel leaves one row of partial sums per row block.  Up to
 // kGsDirect rows are summed by every update block itself; beyond that a
 // small reduction kernel first folds them into kGsGroups rows (the update
@@ -89,7 +107,7 @@ __host__ __device__ inline size_t gs_part_entries(int nrb, int k) {
 }
 
 // Arnoldi step kernels with delayed reorthogonalisation (dcgs2.hip).
-// Partials need gs_part_entries(gs_row_blocks(n), k) entries.
+// Partials need gs_part_entries(sd_row_blocks(n), k) entries.
 // t0, t1 (optional): events stamped at the start of the first and the end
 // of the last kernel of the call (per-kernel timing).
 // dc_dot: (t0, t1) stamp the dot kernel, (r0, r1) the folding kernel if any.
