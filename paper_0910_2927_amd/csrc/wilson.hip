@@ -70,6 +70,12 @@ __global__ __launch_bounds__(kStencilThreads) void k_wilson(StencilGeom g, const
   const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
   const int s = blockIdx.x * kSitesPerBlock + lane;
   const bool act = s < g.V;
+  // the combining waves load their diagonal terms before the hop phase,
+  // so that they are in registers after the barrier
+  TI xd[4];
+  if (h < 3 && act)
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) xd[sp] = in[(sp * 3 + h) * g.V + s];
   if (act) {
     int r = s;
     const int x = r % g.Lx; r /= g.Lx;
@@ -105,7 +111,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_wilson(StencilGeom g, const
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp) {
     const int c = sp * 3 + a;
-    const double2 xin = ld(in + c * g.V + s);
+    const double2 xin = cvt(xd[sp]);
     double2 v = cadd(xin, acc[sp]);                    // D_W psi
     if (sp >= 2) v = make_double2(-v.x, -v.y);         // gamma5
     if constexpr (MODE == 0) {

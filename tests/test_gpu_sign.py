@@ -225,3 +225,20 @@ def test_projection_step_keeps_the_deflated_part_out():
     assert on.converged and err_on <= TOL_FP64
     assert np.max(on.leaks / on.betas) < 1e-9
     assert off.leaks[-1] / off.betas[-1] > 100 * np.max(on.leaks / on.betas)
+
+
+@pytest.mark.parametrize("k,s", [(130, 8), (256, 32)])
+def test_longest_restart_and_most_poles(k, s):
+    """The size limits of the library: k up to 256 (four columns per lane in
+    the small solves) and 64 first-order poles, against the oracle."""
+    from paper_0910_2927_amd import api
+    dims = (2, 3, 4, 5)
+    V, U, b, A = _problem(dims, 0.5, 0.3, 97, 98)
+    sig, om = rational.kl_first_order(s, 1.3)
+    announce(f"sign_apply 2x3x4x5 k={k} poles={2 * s}")
+    op = make_op(U, dims, 0.25, 0.3)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, k, tol=1e-12, max_cycles=100)
+    assert res.converged
+    err = rel(from_dev(res.x, V), xstar.xstar_dense(A, b, sig, om))
+    print(f"k={k} N={2 * s}: cycles={res.cycles} err={err:.2e}")
+    assert err <= TOL_FP64
