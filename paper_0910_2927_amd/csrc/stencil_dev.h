@@ -21,6 +21,21 @@ struct StencilGeom {
   double tsign;   // -1 antiperiodic, +1 periodic (applied on the t wrap)
 };
 
+// The hardware deals workgroups to the 8 XCDs in turn (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  Renumbered, XCD x takes runs of
+// kRun consecutive site blocks (2048 sites) instead of every 8th block, so
+// the neighbours a block reads in y, and mostly in z, are sites its own
+// XCD fetched just before.  The 8 runs in flight together stay adjacent in
+// memory (whole-range slices per XCD alias at power-of-two volumes and
+// were slower at 32^4).  Blocks past the last full set of 8 runs keep their
+// number; a bijection of [0, nb).
+__device__ inline int xcd_runs(int b, int nb) {
+  constexpr int kXcds = 8, kRun = 32;
+  if (b >= nb / (kXcds * kRun) * (kXcds * kRun)) return b;
+  const int x = b % kXcds, i = b / kXcds;
+  return (i / kRun) * (kXcds * kRun) + x * kRun + i % kRun;
+}
+
 // multiply by one of {+1, +i, -1, -i}
 template <int P> __device__ inline double2 ph(double2 z) {
   if constexpr (P == 0) return z;

@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_wilson(StencilGeom g, const
   const double sc = (MODE == 0 && in_scale) ? *in_scale : 1.0;
   __shared__ double2 hs[8][6][64];
   const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
-  const int s = blockIdx.x * kSitesPerBlock + lane;
+  const int s = xcd_runs(blockIdx.x, gridDim.x) * kSitesPerBlock + lane;
   const bool act = s < g.V;
   // the combining waves load their diagonal terms before the hop phase,
   // so that they are in registers after the barrier
