@@ -50,8 +50,9 @@ __global__ __launch_bounds__(kNT) void k_dc_reduce(const double2* __restrict__ p
 }
 
 // Update blocks of kSuThreads threads: the per-block prologue (folding the
-// partial sums, H_j t) is shared by more rows.
+// partial sums, H_j t) is shared by more rows.  Two lanes per row pack.
 constexpr int kSuThreads = 512;
+constexpr int kSuSplit = 2;
 
 template <typename T, bool FINAL>
 __global__ __launch_bounds__(kSuThreads, 4) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
@@ -62,8 +63,9 @@ __global__ __launch_bounds__(kSuThreads, 4) void k_dc_update(T* __restrict__ W, 
                                                           const int* skip) {
   if (skip && *skip) return;
   (void)rpt;
-  dc_update_body<T, FINAL, kSuThreads>(W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
-                                       (int64_t)blockIdx.x * kSuThreads + threadIdx.x, 1, blockIdx.x == 0);
+  dc_update_body<T, FINAL, kSuThreads, kSuSplit>(
+      W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
+      (int64_t)blockIdx.x * (kSuThreads / kSuSplit) + threadIdx.x / kSuSplit, 1, blockIdx.x == 0);
 }
 
 }  // namespace
@@ -104,7 +106,7 @@ hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const
   const int pr = 2 * j + 2;
   const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
   const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
-  const int64_t rows_per_block = (int64_t)kSuThreads * Pk<T>::P;   // one row pack per thread here
+  const int64_t rows_per_block = (int64_t)(kSuThreads / kSuSplit) * Pk<T>::P;   // one row pack per lane pair
   const unsigned nb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
   const bool ext = t0 || t1;
   if (final_pass && ext)

@@ -74,6 +74,66 @@ __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, i
   }
 }
 
+// Exchange of a double with lane ^ M: DPP quad permutations for M = 1, 2,
+// ds_swizzle (bit mode, within 32 lanes) for M = 4, 8, 16, a permute for 32.
+template <int M>
+__device__ inline double xor_lane(double v) {
+  if constexpr (M == 1) {
+    return dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  } else if constexpr (M == 2) {
+    return dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  } else if constexpr (M < 32) {
+    constexpr int kPat = 0x1F | (M << 10);   // and_mask 31, or_mask 0, xor_mask M
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), kPat);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), kPat);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __shfl_xor(v, M, 64);
+  }
+}
+
+// Butterfly stages S.. of a reduce-scatter over the wave: at stage S the
+// lanes with bit S clear keep the first H = ceil(C/2) of their C values,
+// the others the rest (a missing last value reads as 0), and each adds its
+// partner's copy of what it keeps.  idx accumulates the position of the
+// kept range in the original list, real the number of its entries that
+// are not padding.
+template <int S, int C, int N>
+__device__ inline void scatter_stages(double (&v)[N], int lane, int& idx, int& real) {
+  if constexpr (S < 6) {
+    constexpr int M = 1 << S, H = (C + 1) / 2;
+    const bool up = (lane & M) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double lo = v[i];
+      const double hi = (H + i < C) ? v[H + i] : 0.0;
+      v[i] = (up ? hi : lo) + xor_lane<M>(up ? lo : hi);
+    }
+    if (up) {
+      idx += H;
+      real -= H;
+    } else {
+      real = min(real, H);
+    }
+    scatter_stages<S + 1, H, N>(v, lane, idx, real);
+  }
+}
+
+// Sums over the 64 lanes of N values per lane (N <= 64) with about N
+// exchanges instead of the 6 N of one wave_sum per value: afterwards v[0]
+// of the returned lane-dependent index d holds the total of value d; every
+// d < N is held by exactly one lane, the other lanes return -1.  The order
+// of additions is fixed.
+template <int N>
+__device__ inline int wave_scatter_sum(double (&v)[N], int lane) {
+  static_assert(N >= 2 && N <= 64, "one value per lane at most");
+  int idx = 0, real = N;
+  scatter_stages<0, N, N>(v, lane, idx, real);
+  return real > 0 ? idx : -1;
+}
+
+constexpr int kRsVals = 4 * VC + 4;   // doubles per lane of the dot kernel
+
 // Rows of one dot block: every load of a row pack is issued before any of
 // it is used, so a wave has VC + 2 loads in flight.  FULL: the chunk holds
 // VC vectors (no masking); otherwise vectors past cnt re-read a valid
@@ -127,7 +187,6 @@ template <typename T, int BT = NT>
 __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, int has_z,
                                    int64_t n, int rpt, double2* __restrict__ part, int rb, int ch) {
   constexpr int BW = BT / 64;
-  __shared__ double2 red[BW][2 * VC + 2];
   const int i0 = ch * VC;
   const int cnt = max(0, min(VC, j - i0));
   double2 at[VC], ap[VC];
@@ -143,41 +202,42 @@ __device__ inline void dc_dot_body(const T* __restrict__ W, int64_t ldq, int j, 
     if (cnt == VC) dot_rows<T, false, true, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
     else dot_rows<T, false, false, BT>(W, ldq, j, i0, cnt, n, rpt, base, first, at, ap, aa, ag);
   }
+  // 4 VC + 4 doubles per lane (t, p, alpha with a zero imaginary part,
+  // gamma), summed over the wave by a reduce-scatter, then over the waves
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double v[kRsVals];
 #pragma unroll
   for (int c = 0; c < VC; ++c) {
-    at[c].x = wave_sum(at[c].x);
-    at[c].y = wave_sum(at[c].y);
-    ap[c].x = wave_sum(ap[c].x);
-    ap[c].y = wave_sum(ap[c].y);
+    v[2 * c] = at[c].x;
+    v[2 * c + 1] = at[c].y;
+    v[2 * (VC + c)] = ap[c].x;
+    v[2 * (VC + c) + 1] = ap[c].y;
   }
-  aa.x = wave_sum(aa.x);
-  ag.x = wave_sum(ag.x);
-  ag.y = wave_sum(ag.y);
-  if (lane == 0) {
-#pragma unroll
-    for (int c = 0; c < VC; ++c) {
-      red[wid][c] = at[c];
-      red[wid][VC + c] = ap[c];
-    }
-    red[wid][2 * VC] = aa;
-    red[wid][2 * VC + 1] = ag;
-  }
+  v[4 * VC] = aa.x;
+  v[4 * VC + 1] = 0.0;
+  v[4 * VC + 2] = ag.x;
+  v[4 * VC + 3] = ag.y;
+  const int d = wave_scatter_sum(v, lane);
+  __shared__ double red[BW][kRsVals];
+  if (d >= 0) red[wid][d] = v[0];
   __syncthreads();
   const int pr = 2 * j + 2;
   double2* dst = part + (size_t)rb * pr;
   const int t = threadIdx.x;
-  if (t < 2 * VC + 2) {
-    double2 s = red[0][t];
+  if (t < kRsVals) {
+    double s = red[0][t];
 #pragma unroll
-    for (int w = 1; w < BW; ++w) s = cadd(s, red[w][t]);
-    if (t < VC) {
-      if (t < cnt) dst[i0 + t] = s;
-    } else if (t < 2 * VC) {
-      if (t - VC < cnt) dst[j + i0 + (t - VC)] = s;
+    for (int w = 1; w < BW; ++w) s += red[w][t];
+    const int c = t >> 1;   // complex entry, t & 1 its real or imaginary part
+    int o = -1;
+    if (c < VC) {
+      if (c < cnt) o = i0 + c;
+    } else if (c < 2 * VC) {
+      if (c - VC < cnt) o = j + i0 + (c - VC);
     } else if (ch == 0) {
-      dst[2 * j + (t - 2 * VC)] = s;
+      o = 2 * j + (c - 2 * VC);
     }
+    if (o >= 0) reinterpret_cast<double*>(dst + o)[t & 1] = s;
   }
 }
 
@@ -216,9 +276,14 @@ __device__ inline void dc_reduce_body(const double2* __restrict__ part, int nrb,
 // Second pass of u_j and (unless FINAL) first pass of the next vector.
 // `fresh`: first step after a thick restart of the eigensolver, where the
 // columns before j already hold the restarted Rayleigh quotient (kept as is).
-// The thread updates row packs r0, r0 + BT, ..., urt of them (the block's
-// reduction of the partial dots is shared by its BT * urt packs).
-template <typename T, bool FINAL, int BT = NT>
+// The thread updates row packs r0, r0 + BT / SPLIT, ..., urt of them (the
+// block's reduction of the partial dots is shared by its BT * urt / SPLIT
+// packs).  SPLIT > 1: that many adjacent lanes share a row pack, each
+// summing every SPLIT-th basis vector with 16 / SPLIT loads in flight, which
+// shortens the chain of dependent loads per thread; they combine their sums
+// by exchanges within the quad, the first lane writes v_j and the last one
+// u_{j+1}.
+template <typename T, bool FINAL, int BT = NT, int SPLIT = 1>
 __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int64_t n,
                                       const double2* __restrict__ part, int nrb,
                                       const ArnoldiDev& arn, const double2* __restrict__ s_prev,
@@ -349,48 +414,75 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
       }
     __syncthreads();
   }
+  static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "1, 2 or 4 lanes per row pack");
   using K = Pk<T>;
   using PT = typename K::type;
   PT* u = reinterpret_cast<PT*>(W + (int64_t)j * ldq);
   PT* zv = reinterpret_cast<PT*>(W + (int64_t)(j + 1) * ldq);
+  const int sub = SPLIT > 1 ? (int)(threadIdx.x & (SPLIT - 1)) : 0;
   for (int q = 0; q < urt; ++q) {
-    const int64_t rp = r0 + (int64_t)q * BT;
-    if (rp * K::P >= n) return;
+    const int64_t rp = r0 + (int64_t)q * (BT / SPLIT);
+    if (rp * K::P >= n) return;   // the lanes of a row pack leave together
     double2 at[K::P], ae[K::P];
 #pragma unroll
     for (int p = 0; p < K::P; ++p) at[p] = ae[p] = z2();
-    constexpr int B = 16;   // basis loads in flight per thread
+    constexpr int B = 16 / SPLIT;   // basis loads in flight per thread
     const PT ru = u[rp];
     PT rz;
     if (!FINAL) rz = zv[rp];
-    int i = 0;
-    for (; i + B <= j; i += B) {
+    int i = sub;   // vectors i, i + SPLIT, ...
+    for (; i + SPLIT * (B - 1) < j; i += SPLIT * B) {
       PT raw[B];
 #pragma unroll
-      for (int b = 0; b < B; ++b) raw[b] = reinterpret_cast<const PT*>(W + (int64_t)(i + b) * ldq)[rp];
+      for (int b = 0; b < B; ++b)
+        raw[b] = reinterpret_cast<const PT*>(W + (int64_t)(i + SPLIT * b) * ldq)[rp];
 #pragma unroll
       for (int b = 0; b < B; ++b)
 #pragma unroll
         for (int p = 0; p < K::P; ++p) {
           const double2 v = K::get(raw[b], p);
-          at[p] = cadd(at[p], cmul(v, ct[i + b]));
-          if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + b]));
+          at[p] = cadd(at[p], cmul(v, ct[i + SPLIT * b]));
+          if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + SPLIT * b]));
         }
     }
-    if (i < j) {   // the last j - i < B vectors, with clamped (valid) addresses
+    if (i < j) {   // the last vectors of this lane, with clamped (valid) addresses
       PT raw[B];
 #pragma unroll
       for (int b = 0; b < B; ++b)
-        raw[b] = reinterpret_cast<const PT*>(W + (int64_t)min(i + b, j - 1) * ldq)[rp];
+        raw[b] = reinterpret_cast<const PT*>(W + (int64_t)min(i + SPLIT * b, j - 1) * ldq)[rp];
 #pragma unroll
       for (int b = 0; b < B; ++b)
-        if (i + b < j)
+        if (i + SPLIT * b < j)
 #pragma unroll
           for (int p = 0; p < K::P; ++p) {
             const double2 v = K::get(raw[b], p);
-            at[p] = cadd(at[p], cmul(v, ct[i + b]));
-            if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + b]));
+            at[p] = cadd(at[p], cmul(v, ct[i + SPLIT * b]));
+            if (!FINAL) ae[p] = cadd(ae[p], cmul(v, ce[i + SPLIT * b]));
           }
+    }
+    // a + b on one lane, b + a on the other: every lane of the row pack
+    // ends with the same sums
+    if constexpr (SPLIT >= 2) {
+#pragma unroll
+      for (int p = 0; p < K::P; ++p) {
+        at[p].x += xor_lane<1>(at[p].x);
+        at[p].y += xor_lane<1>(at[p].y);
+        if (!FINAL) {
+          ae[p].x += xor_lane<1>(ae[p].x);
+          ae[p].y += xor_lane<1>(ae[p].y);
+        }
+      }
+    }
+    if constexpr (SPLIT == 4) {
+#pragma unroll
+      for (int p = 0; p < K::P; ++p) {
+        at[p].x += xor_lane<2>(at[p].x);
+        at[p].y += xor_lane<2>(at[p].y);
+        if (!FINAL) {
+          ae[p].x += xor_lane<2>(ae[p].x);
+          ae[p].y += xor_lane<2>(ae[p].y);
+        }
+      }
     }
     PT vo, uo;
 #pragma unroll
@@ -399,8 +491,8 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
       K::set(vo, p, cscale(csub(uv, at[p]), ib));                                 // v_j
       if (!FINAL) K::set(uo, p, csub(csub(cscale(K::get(rz, p), ib), cmul(cd, uv)), ae[p]));   // u_{j+1}
     }
-    u[rp] = vo;
-    if (!FINAL) zv[rp] = uo;
+    if (sub == 0) u[rp] = vo;
+    if (!FINAL && sub == SPLIT - 1) zv[rp] = uo;
   }
 }
 
