@@ -50,22 +50,39 @@ __global__ __launch_bounds__(kNT) void k_dc_reduce(const double2* __restrict__ p
 }
 
 // Update blocks of kSuThreads threads: the per-block prologue (folding the
-// partial sums, H_j t) is shared by more rows.  Two lanes per row pack.
+// partial sums, H_j t) is shared by more rows.  SPLIT lanes per row pack:
+// 2 when one lane per pack would leave CUs idle (small n, latency-bound),
+// else 1 (the basis pass is bandwidth-bound and the pair's repeated loads
+// of u_j and z only cost).
 constexpr int kSuThreads = 512;
-constexpr int kSuSplit = 2;
+constexpr int kCUs = 256;
 
-template <typename T, bool FINAL>
+template <typename T, bool FINAL, int SPLIT>
 __global__ __launch_bounds__(kSuThreads, 4) void k_dc_update(T* __restrict__ W, int64_t ldq, int j, int64_t n,
-                                                          int rpt, const double2* __restrict__ part,
+                                                          const double2* __restrict__ part,
                                                           int nrb, ArnoldiDev arn,
                                                           const double2* __restrict__ s_prev,
                                                           double2* __restrict__ s_cur, int fresh,
                                                           const int* skip) {
   if (skip && *skip) return;
-  (void)rpt;
-  dc_update_body<T, FINAL, kSuThreads, kSuSplit>(
+  dc_update_body<T, FINAL, kSuThreads, SPLIT>(
       W, ldq, j, n, part, nrb, arn, s_prev, s_cur, fresh,
-      (int64_t)blockIdx.x * (kSuThreads / kSuSplit) + threadIdx.x / kSuSplit, 1, blockIdx.x == 0);
+      (int64_t)blockIdx.x * (kSuThreads / SPLIT) + threadIdx.x / SPLIT, 1, blockIdx.x == 0);
+}
+
+template <typename T, bool FINAL, int SPLIT>
+hipError_t launch_update(T* W, int64_t ldq, int j, int64_t n, const double2* src, int nrows,
+                         const ArnoldiDev& arn, const double2* s_prev, double2* s_cur, bool fresh,
+                         const int* skip, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+  const int64_t rows_per_block = (int64_t)(kSuThreads / SPLIT) * Pk<T>::P;   // one row pack per SPLIT lanes
+  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block));
+  if (t0 || t1)
+    hipExtLaunchKernelGGL((k_dc_update<T, FINAL, SPLIT>), grid, dim3(kSuThreads), 0, s, t0, t1, 0, W, ldq, j,
+                          n, src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
+  else
+    hipLaunchKernelGGL((k_dc_update<T, FINAL, SPLIT>), grid, dim3(kSuThreads), 0, s, W, ldq, j, n, src, nrows,
+                       arn, s_prev, s_cur, fresh ? 1 : 0, skip);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -106,22 +123,12 @@ hipError_t dc_update(T* W, int64_t ldq, int j, bool final_pass, int64_t n, const
   const int pr = 2 * j + 2;
   const double2* src = gs_reduced(nrb) ? part + (size_t)nrb * pr : part;
   const int nrows = gs_reduced(nrb) ? kGsGroups : nrb;
-  const int64_t rows_per_block = (int64_t)(kSuThreads / kSuSplit) * Pk<T>::P;   // one row pack per lane pair
-  const unsigned nb = (unsigned)((n + rows_per_block - 1) / rows_per_block);
-  const bool ext = t0 || t1;
-  if (final_pass && ext)
-    hipExtLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kSuThreads), 0, s, t0, t1, 0, W, ldq, j, n, 1,
-                          src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
-  else if (final_pass)
-    hipLaunchKernelGGL((k_dc_update<T, true>), dim3(nb), dim3(kSuThreads), 0, s, W, ldq, j, n, 1, src, nrows,
-                       arn, s_prev, s_cur, fresh ? 1 : 0, skip);
-  else if (ext)
-    hipExtLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kSuThreads), 0, s, t0, t1, 0, W, ldq, j, n, 1,
-                          src, nrows, arn, s_prev, s_cur, fresh ? 1 : 0, skip);
-  else
-    hipLaunchKernelGGL((k_dc_update<T, false>), dim3(nb), dim3(kSuThreads), 0, s, W, ldq, j, n, 1, src, nrows,
-                       arn, s_prev, s_cur, fresh ? 1 : 0, skip);
-  return hipGetLastError();
+  const bool split = (n + (int64_t)kSuThreads * Pk<T>::P - 1) / ((int64_t)kSuThreads * Pk<T>::P) < kCUs;
+  if (final_pass)
+    return split ? launch_update<T, true, 2>(W, ldq, j, n, src, nrows, arn, s_prev, s_cur, fresh, skip, s, t0, t1)
+                 : launch_update<T, true, 1>(W, ldq, j, n, src, nrows, arn, s_prev, s_cur, fresh, skip, s, t0, t1);
+  return split ? launch_update<T, false, 2>(W, ldq, j, n, src, nrows, arn, s_prev, s_cur, fresh, skip, s, t0, t1)
+               : launch_update<T, false, 1>(W, ldq, j, n, src, nrows, arn, s_prev, s_cur, fresh, skip, s, t0, t1);
 }
 
 template hipError_t dc_dot<double2>(const double2*, int64_t, int, bool, int64_t, double2*,
