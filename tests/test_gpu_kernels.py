@@ -144,3 +144,50 @@ def test_deflate_project_matches_oracle():
     assert rel(coeff.cpu().numpy(), L.conj().T @ b) < 1e-12
     assert rel(from_dev(r, V), xstar.deflated_source(b, R, L)) < 1e-12
     assert rel(from_dev(xp, V), xstar.x_p(b, R, L, F)) < 1e-12
+
+
+# 11 x 12 x 13 x 14 = 24 024 sites: 376 stencil blocks of 64 sites, so the
+# first 256 run in the per-XCD order and the rest (with a ragged last block)
+# in plain order; n = 288 288 rows fills the update grid with one lane per
+# row pack in both precisions (the smaller lattices above take two).
+BIG = (11, 12, 13, 14)
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_wilson_apply_renumbered_blocks(adjoint):
+    import torch
+    from paper_0910_2927_amd import api
+    V = si.lattice_volume(BIG)
+    U = si.gauge_links(BIG, 0.7, 71)
+    psi = si.gaussian_source(12 * V, 72)
+    A = dirac.hw_csr(U, BIG, 0.25, -0.3 if adjoint else 0.3)
+    ref = A @ psi
+    announce(f"wilson 11x12x13x14 adjoint={adjoint}")
+    op = make_op(U, BIG, 0.25, 0.3, True, with_c64=True)
+    out = from_dev(api.wilson_apply(op, to_dev(psi, V), adjoint=adjoint), V)
+    assert rel(out, ref) < 1e-14
+    out64 = from_dev(api.wilson_apply(op, to_dev(psi, V, torch.complex64), adjoint=adjoint), V)
+    assert np.max(np.abs(out64 - ref)) <= 2e-6 * np.max(np.abs(ref))   # float storage
+
+
+def test_arnoldi_cycle_one_lane_update_path():
+    import torch
+    from paper_0910_2927_amd import api
+    V = si.lattice_volume(BIG)
+    k = 12
+    U = si.gauge_links(BIG, 0.7, 73)
+    b = si.gaussian_source(12 * V, 74)
+    A = dirac.hw_csr(U, BIG, 0.25, 0.3)
+    Vo, Ho, ko = krylov.arnoldi(lambda v: A @ v, b / np.linalg.norm(b), k)
+    announce(f"arnoldi 11x12x13x14 k={k} complex double and complex float")
+    op = make_op(U, BIG, 0.25, 0.3, True, with_c64=True)
+    for dt, tol_h, tol_o in ((torch.complex128, 1e-10, 1e-12), (torch.complex64, 1e-5, 1e-5)):
+        Vd, Hd, kd = api.arnoldi_cycle(op, to_dev(b, V, dt), k)
+        H = Hd.cpu().numpy()
+        assert kd == ko == k
+        err_h = np.max(np.abs(H - Ho)) / np.max(np.abs(Ho))
+        Vb = np.stack([from_dev(Vd[j], V) for j in range(k + 1)], axis=1)
+        err_o = np.linalg.norm(Vb.conj().T @ Vb - np.eye(k + 1))
+        err_r = np.linalg.norm(A @ Vb[:, :k] - Vb @ H) / np.linalg.norm(H)
+        print(f"{dt}: H {err_h:.1e}, orthonormality {err_o:.1e}, Arnoldi relation {err_r:.1e}")
+        assert err_h <= tol_h and err_o < tol_o and err_r < tol_o
