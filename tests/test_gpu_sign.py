@@ -119,7 +119,7 @@ def test_restart_length_independence_and_divergence():
                          raise_on_error=False)
     assert res.status == _lib.SK_ERR_NOCONV and not res.converged
     # (the exact cycle at which growth passes 1e10 is rounding-sensitive in a
-    # divergent iteration, so only the verdict is compared)
+    # divergent iteration, so only the outcome is compared)
 
 
 def test_error_paths_forced_from_the_host():
