@@ -1,0 +1,87 @@
+"""Invariants of the sign_apply solve at the 10^4 headline lattice (mu = 0.3,
+eps = 0.7, 16 poles at c = 2.422, k = 60, m = 40 deflated by the GPU
+eigensolver), complex double, where no dense oracle exists.
+
+Algorithm 1 converges to x*(b) = R F L^H b + sum_i omega_i (H - sigma_i)^{-1}
+(I - R L^H) b (Sect. 4-5), a linear map that commutes with H = H_W when R,
+L span right and left invariant subspaces.  Hence, each to the solve
+tolerance:
+  - linearity:   x(a b1 + c b2) = a x(b1) + c x(b2);
+  - commutation: x(H b) = H x(b);
+  - gauge covariance: with U_nu(x) -> Om(x) U_nu(x) Om(x+nu)^+ the operator
+    becomes Om H Om^+, its deflation data (Om R, Om L, F), and x(Om b) = Om x(b);
+  - adjoint identity: the pole set is closed under conjugation with real
+    weights, so g(H)^+ = g(H^+) and H^+ = H(-mu) is deflated by (L, R, F^H):
+    <eta, x(b)> = <x'(eta), b>.
+Each solve is within ~1e-11 of x*; the identities are checked at 1e-8.
+"""
+import numpy as np
+import pytest
+
+import skinputs as si
+from skinputs.configs import CONFIGS
+from oracle import dirac, rational
+from tests.gpu_util import make_op, to_dev, from_dev, vecs_to_dev, rel, announce
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+def test_headline_lattice_invariants():
+    import torch
+    from paper_0910_2927_amd import api
+    cfg = CONFIGS["c3"]
+    mu = 0.3
+    dims, V, n = cfg.dims, cfg.V, cfg.n
+    U = si.gauge_links(dims, cfg.eps, si.seed_for(cfg.L, "gauge"))
+    sig, om = rational.kl_first_order(cfg.s, cfg.scales[mu])
+    op = make_op(U, dims, cfg.kappa, mu, cfg.antiperiodic_t)
+    announce("invariants 10^4: deflation eigensolve m=40")
+    R, Lv, F, _, _ = api.deflation_eigensolve(op, cfg.m, nev_extra=16, tol=1e-12)
+
+    def solve(o, b, Rr, Ll, Ff, what):
+        announce(f"invariants 10^4: solve {what}")
+        res = api.sign_apply(o, b, sig, om, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles,
+                             R=Rr, Lv=Ll, F=Ff)
+        assert res.converged, what
+        return res.x
+
+    b1c = si.gaussian_source(n, 801)
+    b1, b2 = to_dev(b1c, V), to_dev(si.gaussian_source(n, 802), V)
+    x1 = solve(op, b1, R, Lv, F, "b1")
+    x2 = solve(op, b2, R, Lv, F, "b2")
+    x1c = from_dev(x1, V)
+
+    a, c = 0.7 - 0.2j, -1.3 + 0.4j
+    x12 = solve(op, a * b1 + c * b2, R, Lv, F, "a b1 + c b2")
+    e_lin = rel(from_dev(x12, V), from_dev(a * x1 + c * x2, V))
+
+    hx1 = from_dev(api.wilson_apply(op, x1), V)
+    xh = solve(op, api.wilson_apply(op, b1), R, Lv, F, "H b1")
+    e_com = rel(from_dev(xh, V), hx1)
+
+    Om = si.gauge_links((V, 1, 1, 1), 1.3, 804)[:, 0]          # Om(x) in SU(3)
+    fwd = dirac.neighbours(dims)[0]
+    Ug = np.einsum("sab,snbc,sndc->snad", Om, U, Om[fwd].conj())
+
+    def gt(v):
+        return np.einsum("sab,sib->sia", Om, v.reshape(V, 4, 3)).reshape(-1)
+
+    Rg = vecs_to_dev(np.stack([gt(from_dev(R[i], V)) for i in range(cfg.m)], axis=1), V)
+    Lg = vecs_to_dev(np.stack([gt(from_dev(Lv[i], V)) for i in range(cfg.m)], axis=1), V)
+    opg = make_op(Ug, dims, cfg.kappa, mu, cfg.antiperiodic_t)
+    xg = solve(opg, to_dev(gt(b1c), V), Rg, Lg, F, "gauge-transformed b1")
+    e_gauge = rel(from_dev(xg, V), gt(x1c))
+
+    opm = make_op(U, dims, cfg.kappa, -mu, cfg.antiperiodic_t)
+    eta = to_dev(si.gaussian_source(n, 803), V)
+    FH = torch.conj_physical(F).transpose(0, 1).contiguous()   # F^H, materialised
+    xe = solve(opm, eta, Lv, R, FH, "H^+ eta")
+    lhs = complex(torch.vdot(eta, x1).item())
+    rhs = complex(torch.vdot(xe, b1).item())
+    e_adj = abs(lhs - rhs) / (torch.linalg.norm(eta).item() * torch.linalg.norm(x1).item())
+
+    print(f"10^4 invariants: linearity {e_lin:.1e}, commutation {e_com:.1e}, "
+          f"gauge {e_gauge:.1e}, adjoint {e_adj:.1e}")
+    assert e_lin < TOL and e_com < TOL and e_gauge < TOL and e_adj < TOL
