@@ -45,10 +45,12 @@ def sign_f_diag(lam):
     return np.diag(np.sign(np.asarray(lam).real)).astype(np.complex128)
 
 
-def lr_dense(A, m, key="abs"):
-    """(R, L, Lambda, F) from a dense eigen-decomposition."""
+def lr_dense(A, m, key="abs", eig=None):
+    """(R, L, Lambda, F) from a dense eigen-decomposition.
+
+    ``eig`` optionally passes a precomputed ``np.linalg.eig(A)``."""
     A = np.asarray(A, dtype=np.complex128)
-    lam, W = np.linalg.eig(A)
+    lam, W = np.linalg.eig(A) if eig is None else eig
     sel, gap = select_critical(lam, m, key)
     Winv = np.linalg.inv(W)
     R = W[:, sel]

@@ -94,10 +94,15 @@ def neighbours(dims):
 
 
 def hw_csr(U: np.ndarray, dims, kappa: float, mu: float,
-           antiperiodic_t: bool = True) -> sp.csr_matrix:
+           antiperiodic_t: bool = True, d_mu: bool = False) -> sp.csr_matrix:
     """H_W = gamma5 D_W(mu) as a CSR matrix of size 12V, from the definition.
 
-    U has the canonical shape (V, 4, 3, 3); row/column index 12 s + 3 spin + colour."""
+    U has the canonical shape (V, 4, 3, 3); row/column index 12 s + 3 spin + colour.
+
+    With ``d_mu`` the exact derivative dH_W/dmu instead: mu enters only
+    through the time-hop factors e^{+mu} (forward) and e^{-mu} (backward),
+    whose derivatives are e^{+mu} and -e^{-mu}; the diagonal and the spatial
+    hops drop out."""
     dims = tuple(int(d) for d in dims)
     V = int(np.prod(dims))
     U = np.asarray(U, dtype=np.complex128).reshape(V, 4, 3, 3)
@@ -109,7 +114,7 @@ def hw_csr(U: np.ndarray, dims, kappa: float, mu: float,
     base_r = np.arange(12)
     sites = np.arange(V)
     # diagonal: gamma5 (x) 1_colour
-    diag = np.kron(g5, np.eye(3))
+    diag = np.kron(g5, np.eye(3)) * (0.0 if d_mu else 1.0)
     for a in range(12):
         for b in range(12):
             if diag[a, b] != 0:
@@ -117,8 +122,12 @@ def hw_csr(U: np.ndarray, dims, kappa: float, mu: float,
                 cols.append(12 * sites + b)
                 vals.append(np.full(V, diag[a, b]))
     for nu in range(4):
+        if d_mu and nu != 3:
+            continue
         ph_f = np.exp(mu) if nu == 3 else 1.0
         ph_b = np.exp(-mu) if nu == 3 else 1.0
+        if d_mu:
+            ph_b = -ph_b
         sgn_f = np.ones(V)
         sgn_b = np.ones(V)
         if nu == 3 and antiperiodic_t:

@@ -10,8 +10,8 @@ theta = 0; mu is the chemical potential of the time hops.
 * ``dense_gradient``: dF = -Re sum_j omega_j z_j^H dH x_j with x_j, z_j from
   dense solves, and dH built from the operator definition itself: H_W is
   real-linear in the link field except for the diagonal gamma5, so
-  dH = hw(dU) - hw(0) with dU = i T_a U on the one link.  dH/dmu by a
-  central difference of the (analytic in mu) matrix, h = 1e-6.
+  dH = hw(dU) - hw(0) with dU = i T_a U on the one link.  dH/dmu exactly:
+  only the time hops carry mu, as e^{+mu} forward and e^{-mu} backward.
 * ``fd_link``: central finite difference of F in one coordinate, from the
   exponentiated links (independent of the formula above).
 """
@@ -77,8 +77,7 @@ def dense_gradient(U, dims, kappa, mu, b, eta, sigma, omega, anti=True, coords=N
         dU[s, nu] = 1j * T[a] @ U[s, nu]
         dH = dirac.hw_csr(dU, dims, kappa, mu, anti) - H0
         grad[(nu, s, a)] = -np.real(sum(o * np.vdot(Z[j], dH @ X[j]) for j, o in enumerate(omega)))
-    h = 1e-6
-    dHmu = (dirac.hw_csr(U, dims, kappa, mu + h, anti) - dirac.hw_csr(U, dims, kappa, mu - h, anti)) / (2 * h)
+    dHmu = dirac.hw_csr(U, dims, kappa, mu, anti, d_mu=True)
     gmu = -np.real(sum(o * np.vdot(Z[j], dHmu @ X[j]) for j, o in enumerate(omega)))
     return grad, gmu
 

@@ -143,12 +143,16 @@ def restarted_fom_lr(matvec, b, sigma, omega, k, R=None, L=None, F=None,
 
 
 def multishift_fom_unrestarted(matvec, rhs, sigma, omega, tol=1e-12, kmax=4000,
-                               check_every=10):
+                               check_every=10, watch=None):
     """Long-recurrence multishift FOM (Sect. 2-3) without restarts.
 
     Grows one Arnoldi basis for K_k(A, rhs) until every shifted FOM residual
     norm |h_{k+1,k}| |e_k^T y^{(i)}| <= tol * ||rhs||.  Returns
-    (sum_i omega_i x^{(i)}, X (N x n), k)."""
+    (sum_i omega_i x^{(i)}, X (N x n), k).
+
+    ``watch`` (indices into sigma) limits the periodic test to those shifts
+    -- with many shifts the k x k solves of every test dominate; once they
+    pass, every shift is tested and the run goes on unless all pass."""
     rhs = np.asarray(rhs, dtype=np.complex128)
     n = rhs.shape[0]
     beta = np.linalg.norm(rhs)
@@ -173,6 +177,10 @@ def multishift_fom_unrestarted(matvec, rhs, sigma, omega, tol=1e-12, kmax=4000,
         if not done:
             V[:, j] = w / hb
         if done or j % check_every == 0 or j == kmax:
+            if watch is not None and not done and j < kmax:
+                _, rw = fom_shifted(H[: j + 1, :j], j, beta, np.ones(len(watch)), sigma[watch])
+                if np.max(np.abs(rw)) > tol * beta:
+                    continue
             Y, rho = fom_shifted(H[: j + 1, :j], j, beta, np.ones(len(sigma)), sigma)
             if done or np.max(np.abs(rho)) <= tol * beta:
                 break

@@ -21,7 +21,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["kl_closed_form", "kl_t2_terms", "kl_t2_form", "kl_first_order",
-           "g_first_order", "two_circle_scale"]
+           "g_first_order"]
 
 
 def kl_closed_form(t, s: int):
@@ -69,9 +69,3 @@ def g_first_order(x, sigma, omega):
     x = np.asarray(x, dtype=np.complex128)
     return sum(o / (x - s_) for s_, o in zip(sigma, omega))
 
-
-def two_circle_scale(m: float, r: float) -> float:
-    """c = ((m + r)(m - r))^{-1/2} for a spectrum inside C(m,r) u C(-m,r)."""
-    if not (0 < r < m):
-        raise ValueError("need 0 < r < m")
-    return float(((m + r) * (m - r)) ** -0.5)

@@ -377,3 +377,85 @@ def test_oracle_gradient_matches_finite_differences_2x4():
         theta[c] = 0.7 + 0.1 * c[2]
     dd = gradient.directional_dense(U, dims, 0.25, 0.3, b, eta, sig, om, theta)
     assert abs(dd - sum(theta[c] * grad[c] for c in coords)) < 1e-10 * max(1, abs(dd))
+
+
+# ---------------------------------------------------------------- ARPACK deflation vs dense
+@pytest.mark.parametrize("dims,m", [((4, 4, 4, 4), 10), (RAGGED, 16)])
+def test_lr_arpack_matches_dense_eig(dims, m):
+    """Sect. 4: the sparse route (ARPACK on A^2, left vectors from A^H, pairing
+    by conjugate eigenvalue, L <- L (R^H L)^{-1}) selects the same eigenvalues
+    as a dense eigendecomposition and builds the same oblique projector
+    P = R L^H and deflated start x_P = R sign(Lambda) L^H b, for both
+    selection keys (|lambda| and |Re lambda|).  P and x_P are unique
+    (eigenvector phases and scales cancel), so they are compared directly;
+    a wrong pairing of left with right vectors, a wrong selection or a
+    missing biorthonormalisation changes them at O(1)."""
+    V = si.lattice_volume(dims)
+    U = si.gauge_links(dims, 0.5, 31)
+    A = dirac.hw_csr(U, dims, 0.25, 0.3)
+    AH = dirac.hw_csr(U, dims, 0.25, -0.3)
+    eig = np.linalg.eig(A.toarray())
+    rng = np.random.default_rng(7)
+    Z = rng.standard_normal((12 * V, 4)) + 1j * rng.standard_normal((12 * V, 4))
+    b = si.gaussian_source(12 * V, 32)
+    for key in ("abs", "re"):
+        Rd, Ld, lamd, Fd = deflation.lr_dense(A.toarray(), m, key=key, eig=eig)
+        Ra, La, lama, Fa = deflation.lr_arpack(A, AH, m, key=key, extra=12)
+        # same eigenvalue set
+        sd = np.sort_complex(lamd)
+        sa = np.sort_complex(lama)
+        assert np.max(np.abs(sd - sa)) < 1e-10 * np.max(np.abs(sd)), key
+        # biorthonormal and an invariant pair
+        assert np.linalg.norm(La.conj().T @ Ra - np.eye(m)) < 1e-10
+        res_r, res_l, _ = deflation.projector_checks(A, Ra, La, lama)
+        assert max(res_r, res_l) < 1e-10
+        # same projector, applied to random vectors; same deflated start
+        assert rel(Ra @ (La.conj().T @ Z), Rd @ (Ld.conj().T @ Z)) < 1e-10, key
+        assert rel(xstar.x_p(b, Ra, La, Fa), xstar.x_p(b, Rd, Ld, Fd)) < 1e-10, key
+    # the two keys really select different sets on this spectrum
+    s_abs = np.sort_complex(deflation.lr_dense(A.toarray(), m, key="abs", eig=eig)[2])
+    s_re = np.sort_complex(deflation.lr_dense(A.toarray(), m, key="re", eig=eig)[2])
+    assert np.max(np.abs(s_abs - s_re)) > 1e-3
+
+
+def test_lr_arpack_pairing_survives_shuffled_left_vectors(monkeypatch):
+    """The pairing of left with right vectors must follow the eigenvalues,
+    not the order ARPACK returns them in: reverse the left set and the
+    projector must not change."""
+    dims = (4, 4, 4, 4)
+    U = si.gauge_links(dims, 0.5, 33)
+    A = dirac.hw_csr(U, dims, 0.25, 0.3)
+    AH = dirac.hw_csr(U, dims, 0.25, -0.3)
+    Ra, La, lama, _ = deflation.lr_arpack(A, AH, 10, extra=10)
+    orig = deflation._arpack_sq
+    calls = {"n": 0}
+
+    def shuffled(M, m, extra, tol):
+        lam, vec, mu2 = orig(M, m, extra, tol)
+        calls["n"] += 1
+        if calls["n"] == 2:                       # the left (A^H) solve
+            return lam[::-1], vec[:, ::-1], mu2[::-1]
+        return lam, vec, mu2
+
+    monkeypatch.setattr(deflation, "_arpack_sq", shuffled)
+    Rb, Lb, lamb, _ = deflation.lr_arpack(A, AH, 10, extra=10)
+    z = si.gaussian_source(A.shape[0], 34)
+    assert rel(Rb @ (Lb.conj().T @ z), Ra @ (La.conj().T @ z)) < 1e-10
+
+
+@pytest.mark.parametrize("anti", [True, False])
+def test_exact_mu_derivative_of_hw(anti):
+    """dH_W/dmu written from the definition (only the time hops carry mu)
+    against a central difference of the matrix itself, and against the
+    free-field symbol's derivative in momentum space."""
+    dims = RAGGED
+    U = si.gauge_links(dims, 0.6, 41)
+    mu, h = 0.3, 1e-5
+    dH = dirac.hw_csr(U, dims, 0.25, mu, anti, d_mu=True)
+    fd = (dirac.hw_csr(U, dims, 0.25, mu + h, anti) - dirac.hw_csr(U, dims, 0.25, mu - h, anti)) / (2 * h)
+    assert abs(dH - fd).max() < 1e-9
+    assert abs(dH).max() > 0.1
+    # derivative is nonzero only on time hops: zero spatial links leave it unchanged
+    U0 = U.copy()
+    U0[:, :3] = 0
+    assert abs(dirac.hw_csr(U0, dims, 0.25, mu, anti, d_mu=True) - dH).max() == 0.0
