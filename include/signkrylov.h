@@ -59,6 +59,11 @@ typedef enum {
 } sk_dtype;
 
 typedef enum {
+  SK_METHOD_FOM = 0,    /* restarted multishift FOM, collinear residuals (Algorithm 1) */
+  SK_METHOD_GMRES = 1   /* restarted multishift GMRES (Sect. 2, 3, 5: GMRES-LR) */
+} sk_method;
+
+typedef enum {
   SK_PREC_FP64 = 0,   /* every vector in complex double */
   SK_PREC_MIXED = 1   /* complex-float basis and stencil, double refinement */
 } sk_precision;
@@ -179,6 +184,14 @@ typedef struct {
                                error).  0 = 1e-3; >= 1 = complex float throughout. */
   double* X_shift;          /* device, N x n complex double, or NULL: per-shift
                                solutions of (A - sigma_i) X_i = (I - P) b */
+  int32_t method;           /* SK_METHOD_FOM (Algorithm 1, FOM-LR) or SK_METHOD_GMRES
+                               (GMRES-LR: restarted multishift GMRES, see sign_apply) */
+  int32_t seed;             /* GMRES-LR: index of the pole whose system is solved by
+                               GMRES (-1: the pole nearest the origin) */
+  double resid_tol;         /* SK_PREC_MIXED: the FP64 check of the result (see
+                               sign_apply) accepts shift i when its true residual
+                               ||(I-P)b - (A - sigma_i) X_i|| <= 10 |rho_i| +
+                               resid_tol ||(I-P)b||.  0 = 100 tol. */
 } sk_sign_params;
 
 /* Kernel classes of a solve, for the optional per-kernel timing. */
@@ -217,6 +230,19 @@ typedef struct {
   int32_t hist_cap;         /* capacity of the history arrays */
   sk_kernel_times* times;   /* host, nullable: if set, every kernel of the solve
                                is bracketed by HIP events (slightly slower) */
+  double* hist_rho;         /* host, nullable: per cycle the npoles collinearity
+                               factors |rho_i| (the norms of the shifted residuals
+                               r_i = rho_i (I-P) v_{k+1} the iteration carries),
+                               hist_cap rows of npoles doubles */
+  double* shift_resid;      /* host, nullable: npoles entries, the FP64 true
+                               residuals ||(I-P)b - (A - sigma_i) X_i|| / ||(I-P)b||
+                               at exit (filled when per-shift solutions are kept:
+                               X_shift given, or mixed precision) */
+  double* shift_resid_implicit; /* host, nullable: npoles entries, |rho_i| / ||(I-P)b||
+                               at exit, to compare with shift_resid */
+  int32_t resid_checked;    /* 1 if shift_resid was computed */
+  int32_t resid_ok;         /* 1 if every shift passed the FP64 check */
+  double seconds;           /* host wall-clock time of the call */
 } sk_stats;
 
 /*
@@ -225,6 +251,24 @@ typedef struct {
  * to the stopping rule above.  b, x: device complex double, n entries,
  * no overlap.  stats: host, nullable.  One host read-back per cycle.
  * Returns SK_ERR_NOCONV if max_cycles ran out (x holds the iterate).
+ *
+ * GMRES-LR (p->method = SK_METHOD_GMRES, complex double): the same cycles
+ * of k Arnoldi steps and projection step, but the seed system s solves the
+ * least-squares problem min || beta rho_s e_1 - (Hbar_k - sigma_s I~) y ||
+ * (GMRES), with residual V_{k+1} z, and every other system keeps its
+ * residual collinear with the seed's by solving the (k+1)-square system
+ * [Hbar_k - sigma_i I~, z] [y_i; rho_i'] = beta rho_i e_1; the next cycle
+ * starts from (I - P) V_{k+1} z.  These small problems (O(N k^2)) are solved
+ * on the host in FP64 from the H read back once per cycle.  Same stopping
+ * and divergence rules as FOM-LR.
+ *
+ * Mixed precision keeps the per-shift solutions X_i (in X_shift, or in the
+ * workspace) and, once the stopping rule is met, checks the result in FP64:
+ * N complex-double stencil applications give the true residuals
+ * (I-P)b - (A - sigma_i) X_i, which must stay within 10 |rho_i| (the
+ * residual the iteration carries for shift i) + resid_tol ||(I-P)b||;
+ * otherwise the call returns SK_ERR_NOCONV (x holds the iterate and
+ * stats->shift_resid the residuals).
  */
 size_t sign_apply_workspace_bytes(const sk_operator* op, const sk_sign_params* p);
 int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, double* x,
@@ -344,6 +388,76 @@ size_t deflation_eigensolve_workspace_bytes(const sk_operator* op, const sk_eig_
 int deflation_eigensolve(const sk_operator* op, const sk_eig_params* p, double* R, double* L,
                          double* F, double* lambda, sk_eig_stats* stats, void* ws,
                          size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The direct projection methods Sect. 6 compares FOM-LR with (eq. (direct)):
+ *   x_k = x_P + ||(I - P) b|| V_k sign(M_k) e_1,   x_P = R F L^H b,
+ * no rational approximation and no restarts.
+ *   method 0: M_k = H_k from k Arnoldi steps (CGS2) on A from (I - P) b;
+ *   method 1: M_k = T_k, the tridiagonal matrix of k two-sided Lanczos
+ *             steps (biorthogonal right/left bases of A and A^H = H_W(-mu),
+ *             left start (I - L R^H) v_1; "2sL" of Fig. 1).  Serious
+ *             breakdown (w^H v = 0) returns SK_ERR_SINGULAR.
+ * sign(M_k) by Roberts' method (Newton X <- (X + X^{-1})/2, determinantal
+ * scaling while far from convergence), in FP64 on the device.  Fewer than
+ * k steps are taken when the Krylov space becomes invariant (the result is
+ * then exact up to the deflated part).
+ *   k: 1..256;  m, R, L, F as in sk_sign_params (m = 0: no deflation);
+ *   b, x: device complex double, n entries, no overlap;
+ *   S: device, nullable: on exit sign(M_kk), kk x kk column-major;
+ *   stats: host, nullable.
+ * Returns SK_ERR_NOCONV if the Newton iteration did not converge in 100
+ * steps, SK_ERR_SINGULAR if an iterate was singular.  Complex double.
+ */
+typedef struct {
+  int32_t k_done;        /* Krylov steps taken */
+  int32_t breakdown;     /* 1 if the space became invariant before k */
+  int32_t newton_iters;  /* Newton iterations for sign(M_kk) */
+  int32_t pad;
+  double newton_change;  /* relative change of the last Newton iteration */
+  double seconds;        /* host wall-clock time of the call */
+} sk_direct_stats;
+
+size_t direct_sign_workspace_bytes(const sk_operator* op, int method, int k, int m);
+int direct_sign_apply(const sk_operator* op, int method, int k, int m, const double* R,
+                      const double* L, const double* F, const double* b, double* x, double* S,
+                      sk_direct_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * The overlap Dirac operator at chemical potential mu (Sect. 1; the paper
+ * defines it by reference, here in the usual normalisation):
+ *   D(m) = (1 - m/2) (1 + gamma5 sign(H_W)) + m      (massless at m = 0),
+ * with sign(H_W) v computed by sign_apply(op, p, v) -- Algorithm 1 with the
+ * poles, restart length, deflation and precision of p (p->X_shift must be
+ * NULL).  gamma5 = diag(1, 1, -1, -1): components 6..11 of a field.
+ *   overlap_apply: y = D(m) b.  Workspace overlap_workspace_bytes(op, p, 0).
+ *   overlap_solve: x with D(m) x = b by restarted GMRES(k_outer) (classical
+ *     Gram-Schmidt twice, Givens least squares on the host), every operator
+ *     application one sign_apply; stops when the true relative residual
+ *     ||b - D x|| / ||b|| <= 10 tol_outer after the GMRES estimate fell below
+ *     tol_outer, else SK_ERR_NOCONV after max_outer applications.  The inner
+ *     tolerance p->tol must be well below tol_outer.  Workspace
+ *     overlap_workspace_bytes(op, p, k_outer), k_outer in [1, 256].
+ * b, y, x: device complex double, n entries, no overlap.  Errors of the inner
+ * sign_apply are returned as they are (with its message).
+ */
+typedef struct {
+  int32_t outer_iters;    /* operator applications inside GMRES cycles */
+  int32_t restarts;       /* GMRES cycles */
+  int64_t sign_calls;     /* sign_apply calls (including true residuals) */
+  int64_t inner_matvecs;  /* H_W applications of all inner solves */
+  double rel_residual;    /* last true (or estimated) relative residual */
+  int32_t converged;
+  int32_t pad;
+  double seconds;         /* host wall-clock time of the call */
+} sk_overlap_stats;
+
+size_t overlap_workspace_bytes(const sk_operator* op, const sk_sign_params* p, int k_outer);
+int overlap_apply(const sk_operator* op, const sk_sign_params* p, double mass, const double* b,
+                  double* y, sk_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
+int overlap_solve(const sk_operator* op, const sk_sign_params* p, double mass, int k_outer,
+                  int max_outer, double tol_outer, const double* b, double* x,
+                  sk_overlap_stats* stats, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Host helpers exposing the library's small dense FP64 routines (used by the

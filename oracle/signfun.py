@@ -39,13 +39,19 @@ def sign_schur(A: np.ndarray) -> np.ndarray:
 
 
 def sign_newton(A: np.ndarray, tol: float = 1e-14, maxit: int = 100) -> np.ndarray:
+    """Roberts' Newton iteration.  It converges quadratically; in floating
+    point the relative change then levels off at about the unit roundoff
+    times the conditioning of X, so the loop also ends once the change is
+    below 1e-10 and no longer halves (the limit has been reached)."""
     X = np.asarray(A, dtype=np.complex128).copy()
+    d_prev = np.inf
     for _ in range(maxit):
         Xn = 0.5 * (X + np.linalg.inv(X))
         d = np.linalg.norm(Xn - X, 1) / np.linalg.norm(Xn, 1)
         X = Xn
-        if d < tol:
+        if d < tol or (d < 1e-10 and d > 0.5 * d_prev):
             break
+        d_prev = d
     else:
         raise RuntimeError("Newton sign iteration did not converge")
     return X

@@ -23,6 +23,8 @@ SK_C128 = 0
 SK_C64 = 1
 SK_PREC_FP64 = 0
 SK_PREC_MIXED = 1
+SK_METHOD_FOM = 0
+SK_METHOD_GMRES = 1
 
 STATUS_NAMES = {
     SK_OK: "SK_OK", SK_ERR_ARG: "SK_ERR_ARG", SK_ERR_HIP: "SK_ERR_HIP",
@@ -43,7 +45,8 @@ class SkSignParams(C.Structure):
                 ("max_cycles", C.c_int32), ("tol", C.c_double), ("m", C.c_int32),
                 ("R", C.c_void_p), ("L", C.c_void_p), ("F", C.c_void_p),
                 ("project_each_cycle", C.c_int32), ("precision", C.c_int32),
-                ("mixed_switch", C.c_double), ("X_shift", C.c_void_p)]
+                ("mixed_switch", C.c_double), ("X_shift", C.c_void_p),
+                ("method", C.c_int32), ("seed", C.c_int32), ("resid_tol", C.c_double)]
 
 
 SK_KERNEL_CLASSES = ["stencil", "gs_dot", "gs_upd_dot", "gs_upd_norm", "small", "sol_update",
@@ -60,13 +63,27 @@ class SkStats(C.Structure):
                 ("breakdown", C.c_int32), ("final_update_norm", C.c_double),
                 ("x_norm", C.c_double), ("hist_update", C.POINTER(C.c_double)),
                 ("hist_beta", C.POINTER(C.c_double)), ("hist_leak", C.POINTER(C.c_double)),
-                ("hist_cap", C.c_int32), ("times", C.POINTER(SkKernelTimes))]
+                ("hist_cap", C.c_int32), ("times", C.POINTER(SkKernelTimes)),
+                ("hist_rho", C.POINTER(C.c_double)), ("shift_resid", C.POINTER(C.c_double)),
+                ("shift_resid_implicit", C.POINTER(C.c_double)), ("resid_checked", C.c_int32),
+                ("resid_ok", C.c_int32), ("seconds", C.c_double)]
 
 
 class SkBatchSystem(C.Structure):
     _fields_ = [("op", SkOperator), ("b", C.c_void_p), ("x", C.c_void_p), ("k", C.c_int32),
                 ("m", C.c_int32), ("R", C.c_void_p), ("L", C.c_void_p), ("F", C.c_void_p),
                 ("sigma", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double))]
+
+
+class SkDirectStats(C.Structure):
+    _fields_ = [("k_done", C.c_int32), ("breakdown", C.c_int32), ("newton_iters", C.c_int32),
+                ("pad", C.c_int32), ("newton_change", C.c_double), ("seconds", C.c_double)]
+
+
+class SkOverlapStats(C.Structure):
+    _fields_ = [("outer_iters", C.c_int32), ("restarts", C.c_int32), ("sign_calls", C.c_int64),
+                ("inner_matvecs", C.c_int64), ("rel_residual", C.c_double), ("converged", C.c_int32),
+                ("pad", C.c_int32), ("seconds", C.c_double)]
 
 
 class SkEigParams(C.Structure):
@@ -117,6 +134,16 @@ SIGNATURES = [
                                      C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
     ("sk_batched_last_tile", C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     ("sk_batched_set_tile", C.c_int, [C.c_int, C.c_int, C.c_int]),
+    ("direct_sign_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator), C.c_int, C.c_int, C.c_int]),
+    ("direct_sign_apply", C.c_int, [C.POINTER(SkOperator), C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.POINTER(SkDirectStats), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("overlap_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_int]),
+    ("overlap_apply", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_double, C.c_void_p,
+                                C.c_void_p, C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),
+    ("overlap_solve", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_double, C.c_int,
+                                C.c_int, C.c_double, C.c_void_p, C.c_void_p, C.POINTER(SkOverlapStats),
+                                C.c_void_p, C.c_size_t, C.c_void_p]),
     ("sign_apply_backward_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator),
                                                          C.POINTER(SkSignParams)]),
     ("sign_apply_backward", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,

@@ -17,7 +17,8 @@ import torch
 from . import _lib as L
 
 __all__ = ["WilsonOperator", "SignResult", "kl_poles", "wilson_apply", "arnoldi_cycle",
-           "multishift_fom_restart", "deflate_project", "sign_apply", "BatchedSignSolver", "SkError"]
+           "multishift_fom_restart", "deflate_project", "sign_apply", "BatchedSignSolver", "SkError",
+           "direct_sign_apply", "OverlapOperator"]
 
 SkError = L.SkError
 
@@ -231,6 +232,11 @@ class SignResult:
     betas: np.ndarray = field(default_factory=lambda: np.zeros(0))
     leaks: np.ndarray = field(default_factory=lambda: np.zeros(0))
     X_shift: torch.Tensor | None = None
+    rho_hist: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+    shift_resid: np.ndarray | None = None
+    shift_resid_implicit: np.ndarray | None = None
+    resid_ok: bool | None = None
+    seconds: float = 0.0
 
 
 class SignSolver:
@@ -238,7 +244,8 @@ class SignSolver:
 
     def __init__(self, op: WilsonOperator, sigma, omega, k, tol=1e-9, max_cycles=500,
                  R=None, Lv=None, F=None, project_each_cycle=True, precision="fp64",
-                 keep_shift_solutions=False, hist_cap=4096, mixed_switch=0.0):
+                 keep_shift_solutions=False, hist_cap=4096, mixed_switch=0.0, resid_tol=0.0,
+                 residuals=False, method="fom", seed=-1):
         self.lib = L.load()
         if precision in ("mixed", "mixed_c64_only"):
             op.ensure_c64()
@@ -272,7 +279,11 @@ class SignSolver:
         p.precision = L.SK_PREC_FP64 if precision == "fp64" else L.SK_PREC_MIXED
         p.mixed_switch = float(mixed_switch)
         p.X_shift = self.X.data_ptr() if self.X is not None else None
+        p.resid_tol = float(resid_tol)
+        p.method = {"fom": L.SK_METHOD_FOM, "gmres": L.SK_METHOD_GMRES}[method]
+        p.seed = int(seed)
         self.params = p
+        self.residuals = bool(residuals)
         self.opstruct = op.struct()
         nb = self.lib.sign_apply_workspace_bytes(C.byref(self.opstruct), C.byref(p))
         if nb == 0:
@@ -282,6 +293,9 @@ class SignSolver:
         self._hu = (C.c_double * hist_cap)()
         self._hb = (C.c_double * hist_cap)()
         self._hl = (C.c_double * hist_cap)()
+        self._hr = (C.c_double * (hist_cap * self.N))()
+        self._sr = (C.c_double * self.N)()
+        self._si = (C.c_double * self.N)()
 
     def __call__(self, b, x=None, raise_on_error=True):
         _need(b, torch.complex128, self.op.n, "b")
@@ -292,16 +306,26 @@ class SignSolver:
         st.hist_beta = C.cast(self._hb, C.POINTER(C.c_double))
         st.hist_leak = C.cast(self._hl, C.POINTER(C.c_double))
         st.hist_cap = self.hist_cap
+        st.hist_rho = C.cast(self._hr, C.POINTER(C.c_double))
+        if self.residuals:
+            st.shift_resid = C.cast(self._sr, C.POINTER(C.c_double))
+            st.shift_resid_implicit = C.cast(self._si, C.POINTER(C.c_double))
         status = self.lib.sign_apply(C.byref(self.opstruct), C.byref(self.params), _ptr(b), _ptr(x),
                                      C.byref(st), _ptr(self.ws), self.ws.numel(), _stream())
         if raise_on_error and status not in (L.SK_OK,):
             L.check(status)
         nc = min(st.cycles, self.hist_cap)
+        checked = bool(st.resid_checked)
         return SignResult(x=x, status=status, cycles=st.cycles, cycles_c64=st.cycles_c64,
                           matvecs=st.matvecs,
                           converged=bool(st.converged), breakdown=bool(st.breakdown),
                           update_norms=np.array(self._hu[:nc]), betas=np.array(self._hb[:nc]),
-                          leaks=np.array(self._hl[:nc]), X_shift=self.X)
+                          leaks=np.array(self._hl[:nc]), X_shift=self.X,
+                          rho_hist=np.array(self._hr[:nc * self.N]).reshape(nc, self.N),
+                          shift_resid=np.array(self._sr[:]) if checked and self.residuals else None,
+                          shift_resid_implicit=(np.array(self._si[:]) if checked and self.residuals
+                                                else None),
+                          resid_ok=bool(st.resid_ok) if checked else None, seconds=st.seconds)
 
 
 class BatchedSignSolver:
@@ -425,6 +449,76 @@ class BatchedSignSolver:
                                   update_norms=np.array(hu[:nc]), betas=np.array(hb[:nc]),
                                   leaks=np.array(hl[:nc])))
         return out
+
+
+def direct_sign_apply(op: WilsonOperator, b, k, method="arnoldi", R=None, Lv=None, F=None,
+                      return_sign=False):
+    """The direct projection x_P + ||(I-P)b|| V_k sign(M_k) e_1 (library).
+
+    method "arnoldi" (M_k = H_k) or "lanczos" (two-sided Lanczos, M_k = T_k).
+    Returns (x, stats dict[, sign(M_kk) as a (kk, kk) tensor])."""
+    lib = L.load()
+    _need(b, torch.complex128, op.n, "b")
+    mth = {"arnoldi": 0, "lanczos": 1}[method]
+    m = 0 if R is None else int(R.shape[0])
+    Fc = None
+    if m:
+        _need(R, torch.complex128, m * op.n, "R")
+        _need(Lv, torch.complex128, m * op.n, "L")
+        Fc = F.transpose(0, 1).contiguous()
+    s = op.struct()
+    nb = lib.direct_sign_workspace_bytes(C.byref(s), mth, int(k), m)
+    if nb == 0:
+        raise SkError(L.SK_ERR_ARG, "invalid parameters for direct_sign_apply")
+    ws = _workspace(nb, op.device)
+    x = torch.empty_like(b)
+    S = torch.empty(int(k) * int(k), dtype=torch.complex128, device=op.device) if return_sign else None
+    st = L.SkDirectStats()
+    L.check(lib.direct_sign_apply(C.byref(s), mth, int(k), m, _ptr(R), _ptr(Lv), _ptr(Fc), _ptr(b), _ptr(x),
+                                  _ptr(S), C.byref(st), _ptr(ws), ws.numel(), _stream()))
+    stats = {"k_done": st.k_done, "breakdown": bool(st.breakdown), "newton_iters": st.newton_iters,
+             "newton_change": st.newton_change, "seconds": st.seconds}
+    if return_sign:
+        kk = st.k_done
+        return x, stats, S[: kk * kk].reshape(kk, kk).transpose(0, 1)
+    return x, stats
+
+
+class OverlapOperator:
+    """D(m) = (1 - m/2)(1 + gamma5 sign(H_W)) + m with sign(H_W) by sign_apply
+    (the SignSolver's poles, restart length, deflation and precision)."""
+
+    def __init__(self, solver: "SignSolver", mass=0.0, k_outer=30):
+        if solver.X is not None:
+            raise ValueError("the inner solver must not keep per-shift solutions")
+        self.solver, self.mass, self.k_outer = solver, float(mass), int(k_outer)
+        self.lib = L.load()
+        nb = self.lib.overlap_workspace_bytes(C.byref(solver.opstruct), C.byref(solver.params), self.k_outer)
+        if nb == 0:
+            raise SkError(L.SK_ERR_ARG, "invalid parameters for the overlap operator")
+        self.ws = _workspace(nb, solver.op.device)
+
+    def apply(self, b):
+        _need(b, torch.complex128, self.solver.op.n, "b")
+        y = torch.empty_like(b)
+        st = L.SkStats()
+        L.check(self.lib.overlap_apply(C.byref(self.solver.opstruct), C.byref(self.solver.params), self.mass,
+                                       _ptr(b), _ptr(y), C.byref(st), _ptr(self.ws), self.ws.numel(),
+                                       _stream()))
+        return y
+
+    def solve(self, b, tol=1e-8, max_outer=1000, raise_on_error=True):
+        _need(b, torch.complex128, self.solver.op.n, "b")
+        x = torch.empty_like(b)
+        st = L.SkOverlapStats()
+        status = self.lib.overlap_solve(C.byref(self.solver.opstruct), C.byref(self.solver.params), self.mass,
+                                        self.k_outer, int(max_outer), float(tol), _ptr(b), _ptr(x),
+                                        C.byref(st), _ptr(self.ws), self.ws.numel(), _stream())
+        if raise_on_error:
+            L.check(status)
+        return x, {"status": status, "outer_iters": st.outer_iters, "restarts": st.restarts,
+                   "sign_calls": st.sign_calls, "inner_matvecs": st.inner_matvecs,
+                   "rel_residual": st.rel_residual, "converged": bool(st.converged), "seconds": st.seconds}
 
 
 def sign_apply(op, b, sigma, omega, k, **kw):

@@ -751,6 +751,7 @@ int check_batch(int nsys, const sk_batch_system* d, const sk_sign_params* p, cha
   if (p->k < 0 || p->k > kMaxK) return snprintf(msg, len, "k = %d outside [1, %d]", p->k, kMaxK), 0;
   if (p->max_cycles < 1 || !(p->tol > 0.0)) return snprintf(msg, len, "max_cycles and tol must be positive"), 0;
   if (p->precision != SK_PREC_FP64 && p->precision != SK_PREC_MIXED) return snprintf(msg, len, "unknown precision"), 0;
+  if (p->method != SK_METHOD_FOM) return snprintf(msg, len, "the batched solver runs FOM-LR only"), 0;
   if (p->X_shift) return snprintf(msg, len, "per-shift solutions are not available in the batched solver"), 0;
   if (p->mixed_switch < 0.0) return snprintf(msg, len, "mixed_switch must be >= 0"), 0;
   for (int z = 0; z < nsys; ++z) {

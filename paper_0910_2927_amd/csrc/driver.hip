@@ -2,7 +2,9 @@
 // restart loop of Algorithm 1 (restarted FOM-LR(m,k)) built from the
 // kernels in wilson.hip, tsla.hip and small.hip.
 #include "krylov_ws.h"
+#include "dense_host.h"
 
+#include <chrono>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -360,6 +362,9 @@ bool params_ok(const sk_sign_params* p, char* msg, size_t len) {
   if (p->m < 0 || p->m > kMaxDefl) return snprintf(msg, len, "m = %d outside [0, %d]", p->m, kMaxDefl), false;
   if (p->m > 0 && (!p->R || !p->L || !p->F)) return snprintf(msg, len, "m > 0 needs R, L and F"), false;
   if (p->precision != SK_PREC_FP64 && p->precision != SK_PREC_MIXED) return snprintf(msg, len, "unknown precision %d", p->precision), false;
+  if (p->method != SK_METHOD_FOM && p->method != SK_METHOD_GMRES) return snprintf(msg, len, "unknown method %d", p->method), false;
+  if (p->method == SK_METHOD_GMRES && p->precision != SK_PREC_FP64) return snprintf(msg, len, "GMRES-LR runs in complex double only"), false;
+  if (p->method == SK_METHOD_GMRES && (p->seed < -1 || p->seed >= p->npoles)) return snprintf(msg, len, "seed %d outside [-1, %d)", p->seed, p->npoles), false;
   if (!(p->mixed_switch >= 0.0)) return snprintf(msg, len, "mixed_switch must be >= 0"), false;
   return true;
 }
@@ -370,14 +375,62 @@ struct SignWs {
   KrylovWs<double2> w64;
   KrylovWs<float2> w32;
   bool mixed;
+  // per-shift solutions kept in the workspace (mixed precision without a
+  // caller X_shift), and the buffers of the FP64 true-residual check
+  double2* Xint;
+  double2* rhs;       // (I - P) b
+  double2* tmp;       // one shifted residual
+  double* resid2;     // npoles squared residual norms, then ||rhs||^2
+  double2* rnext;     // GMRES-LR: the next restart vector V_{k+1} z
+  double2* zdev;      // GMRES-LR: z (k+1 entries)
 };
 
 size_t carve_sign(Carver& c, SignWs& sw, int64_t n, const sk_sign_params* p) {
   sw.mixed = p->precision == SK_PREC_MIXED;
-  carve_krylov(c, sw.w64, n, p->k, p->npoles, p->m, p->X_shift != nullptr);
+  const bool keep = p->X_shift != nullptr || sw.mixed;
+  carve_krylov(c, sw.w64, n, p->k, p->npoles, p->m, keep);
   std::memcpy(&sw.w32, &sw.w64, sizeof(sw.w32));   // same small arrays
   sw.w32.W = sw.mixed ? c.take<float2>((size_t)(p->k + 1) * n) : nullptr;
+  sw.Xint = (sw.mixed && !p->X_shift) ? c.take<double2>((size_t)p->npoles * n) : nullptr;
+  sw.rhs = keep ? c.take<double2>(n) : nullptr;
+  sw.tmp = keep ? c.take<double2>(n) : nullptr;
+  sw.resid2 = keep ? c.take<double>(p->npoles + 2) : nullptr;
+  sw.rnext = p->method == SK_METHOD_GMRES ? c.take<double2>(n) : nullptr;
+  sw.zdev = p->method == SK_METHOD_GMRES ? c.take<double2>((size_t)p->k + 1) : nullptr;
   return c.off;
+}
+
+// FP64 true residuals of the shifted systems, ||(I-P)b - (A - sigma_i) X_i||,
+// relative to ||(I-P)b||, from N complex-double stencil applications
+// (residual form of the Wilson kernel) and fixed-order norm reductions.
+int true_residuals(const sk_operator* op, const sk_sign_params* p, const PoleSet& ps,
+                   const double2* b, const double2* X, SignWs& sw, int64_t n,
+                   std::vector<double>& rel, double& rhs_norm, hipStream_t s) {
+  KrylovWs<double2>& w = sw.w64;
+  const ArnoldiDev a = arn_of(w, p->k);
+  const int cs = ts_counter_stride(n);
+  const int N = ps.n;
+  // rhs = (I - R L^H) b with the start's coefficients L^H b (still in dc)
+  TsEpiArgs er = epi_of(EPI_XNORM, a);
+  er.dst_scalar = sw.resid2 + N;
+  SK_LAUNCH((ts_update<double2, double2, double2>(p->m > 0 ? (const double2*)p->R : nullptr, n, p->m,
+                                                  w.dc, nullptr, b, sw.rhs, n, 2, er, w.partial,
+                                                  w.counter + 5 * cs, nullptr, s)));
+  for (int i = 0; i < N; ++i) {
+    SK_LAUNCH((launch_wilson_residual<double2>(op, (const double2*)op->links, X + (size_t)i * n,
+                                               sw.rhs, ps.sigma[i], sw.tmp, s)));
+    TsEpiArgs en = epi_of(EPI_XNORM, a);
+    en.dst_scalar = sw.resid2 + i;
+    SK_LAUNCH((ts_dot<double2, double2>(nullptr, n, 0, sw.tmp, n, true, en, w.partial,
+                                        w.counter + 4 * cs, nullptr, s)));
+  }
+  std::vector<double> r2(N + 1);
+  SK_HIP(hipMemcpyAsync(r2.data(), sw.resid2, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+  SK_HIP(hipStreamSynchronize(s));
+  rhs_norm = std::sqrt(r2[N]);
+  rel.assign(N, 0.0);
+  for (int i = 0; i < N; ++i) rel[i] = rhs_norm > 0.0 ? std::sqrt(r2[i]) / rhs_norm : std::sqrt(r2[i]);
+  return SK_OK;
 }
 
 template <typename T> KrylovWs<T>& view(SignWs& sw);
@@ -495,13 +548,13 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
               sk_stats* stats, void* ws, hipStream_t s) {
   const int64_t n = 12 * volume_of(op);
   const int k = p->k, m = p->m, N = p->npoles;
-  double2* X = (double2*)p->X_shift;
   const double2* R = (const double2*)p->R;
   const double2* Lv = (const double2*)p->L;
   Carver c;
   c.base = (char*)ws;
   SignWs sw;
   carve_sign(c, sw, n, p);
+  double2* X = p->X_shift ? (double2*)p->X_shift : sw.Xint;
   KrylovWs<double2>& w = sw.w64;
   PoleSet ps;
   SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
@@ -551,6 +604,8 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     stats->breakdown = 0;
     stats->final_update_norm = 0.0;
     stats->x_norm = 0.0;
+    stats->resid_checked = 0;
+    stats->resid_ok = 0;
   }
   if (hs.nonfinite || !std::isfinite(hs.beta)) {
     set_error("source contains non-finite values");
@@ -571,6 +626,8 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   int small = 0, status = SK_ERR_NOCONV;
   double first_upd = 0.0;
   bool diverged = false;
+  std::vector<double2> rho_h(N);
+  const bool want_rho = stats && stats->hist_rho;
   for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
     // the next cycle's precision is decided before this one is enqueued:
     // once low, it stays low
@@ -579,8 +636,13 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     SK_TRY(run_cycle(!cur ? (low_next ? 1 : 0) : 2, ca, sw, graphs, use_graph));
     low = low_next;
     SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    if (want_rho && cyc < stats->hist_cap)
+      SK_HIP(hipMemcpyAsync(rho_h.data(), w.rho, N * sizeof(double2), hipMemcpyDeviceToHost, s));
     SK_HIP(hipStreamSynchronize(s));
     tm.flush();
+    if (want_rho && cyc < stats->hist_cap)
+      for (int i = 0; i < N; ++i)
+        stats->hist_rho[(size_t)cyc * N + i] = std::sqrt(cabs2(rho_h[i]));
     if (stats) {
       stats->cycles = cyc + 1;
       stats->cycles_c64 += cur ? 1 : 0;
@@ -625,6 +687,282 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   }
   if (stats) stats->converged = (status == SK_OK);
   if (status == SK_ERR_NOCONV && !diverged) set_error("not converged after %d cycles", p->max_cycles);
+  // FP64 check of the per-shift solutions: always in mixed precision (the
+  // complex-float cycles must not have moved the iterate off the residuals
+  // the iteration carries), on request otherwise
+  const bool want_resid = stats && (stats->shift_resid || stats->shift_resid_implicit);
+  if (X && (status == SK_OK || want_resid) && (sw.mixed || want_resid)) {
+    std::vector<double> rel;
+    double rn = 0.0;
+    SK_TRY(true_residuals(op, p, ps, b, X, sw, n, rel, rn, s));
+    SK_HIP(hipMemcpyAsync(rho_h.data(), w.rho, N * sizeof(double2), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipStreamSynchronize(s));
+    const double rtol = p->resid_tol > 0.0 ? p->resid_tol : 100.0 * p->tol;
+    bool ok = true;
+    int worst = 0;
+    for (int i = 0; i < N; ++i) {
+      const double imp = rn > 0.0 ? std::sqrt(cabs2(rho_h[i])) / rn : 0.0;
+      if (stats && stats->shift_resid) stats->shift_resid[i] = rel[i];
+      if (stats && stats->shift_resid_implicit) stats->shift_resid_implicit[i] = imp;
+      if (!(rel[i] <= 10.0 * imp + rtol)) {
+        if (ok || rel[i] > rel[worst]) worst = i;
+        ok = false;
+      }
+    }
+    if (stats) {
+      stats->resid_checked = 1;
+      stats->resid_ok = ok ? 1 : 0;
+    }
+    if (sw.mixed && status == SK_OK && !ok) {
+      set_error("FP64 check failed: true residual of shift %d is %.3e of ||(I-P)b|| (the iteration "
+                "carries %.3e)", worst, rel[worst], std::sqrt(cabs2(rho_h[worst])) / rn);
+      status = SK_ERR_NOCONV;
+      if (stats) stats->converged = 0;
+    }
+  }
+  return status;
+}
+
+// GMRES-LR: the restart loop of sign_impl with the GMRES small problems
+// (seed least squares, collinear residuals for the other poles) solved on
+// the host from H read back once per cycle.
+int gmres_small(int kk, const std::vector<dense::cd>& H, int ld, double beta, std::vector<dense::cd>& rho,
+                const PoleSet& ps, int seed, bool breakdown, std::vector<dense::cd>& Y, std::vector<dense::cd>& z) {
+  using cd = dense::cd;
+  const int N = ps.n;
+  Y.assign((size_t)N * kk, cd(0.0));
+  z.assign(kk + 1, cd(0.0));
+  auto h = [&](int i, int j) { return H[i + (size_t)j * ld]; };
+  auto sig = [&](int i) { return cd(ps.sigma[i].x, ps.sigma[i].y); };
+  if (breakdown) {   // invariant space: every system exactly, from the square H_kk
+    for (int i = 0; i < N; ++i) {
+      std::vector<cd> A((size_t)kk * kk), rhs(kk, cd(0.0));
+      for (int c = 0; c < kk; ++c)
+        for (int r = 0; r < kk; ++r) A[r + (size_t)c * kk] = h(r, c) - (r == c ? sig(i) : cd(0.0));
+      rhs[0] = beta * rho[i];
+      if (!dense::lu_solve(kk, A, rhs, 1)) return SK_ERR_SINGULAR;
+      for (int r = 0; r < kk; ++r) Y[(size_t)i * kk + r] = rhs[r];
+      rho[i] = 0.0;
+    }
+    return SK_OK;
+  }
+  // seed: least squares on the (kk+1) x kk Hessenberg by Givens rotations
+  std::vector<cd> Hs((size_t)(kk + 1) * kk), g(kk + 1, cd(0.0));
+  for (int c = 0; c < kk; ++c)
+    for (int r = 0; r <= kk; ++r) Hs[r + (size_t)c * (kk + 1)] = h(r, c) - (r == c ? sig(seed) : cd(0.0));
+  g[0] = beta * rho[seed];
+  std::vector<cd> G(g);
+  std::vector<double> gc(kk);
+  std::vector<cd> gs(kk);
+  for (int j = 0; j < kk; ++j) {
+    const cd a = Hs[j + (size_t)j * (kk + 1)], b = Hs[j + 1 + (size_t)j * (kk + 1)];
+    const double den = std::sqrt(std::norm(a) + std::norm(b));
+    if (den == 0.0) return SK_ERR_SINGULAR;
+    const cd ph = std::abs(a) > 0.0 ? a / std::abs(a) : cd(1.0);
+    gc[j] = std::abs(a) / den;
+    gs[j] = ph * std::conj(b) / den;
+    for (int c = j; c < kk; ++c) {
+      const cd t = Hs[j + (size_t)c * (kk + 1)], u = Hs[j + 1 + (size_t)c * (kk + 1)];
+      Hs[j + (size_t)c * (kk + 1)] = gc[j] * t + gs[j] * u;
+      Hs[j + 1 + (size_t)c * (kk + 1)] = -std::conj(gs[j]) * t + gc[j] * u;
+    }
+    const cd t = G[j], u = G[j + 1];
+    G[j] = gc[j] * t + gs[j] * u;
+    G[j + 1] = -std::conj(gs[j]) * t + gc[j] * u;
+  }
+  std::vector<cd> ys(kk);
+  for (int i = kk - 1; i >= 0; --i) {
+    cd acc = G[i];
+    for (int q = i + 1; q < kk; ++q) acc -= Hs[i + (size_t)q * (kk + 1)] * ys[q];
+    const cd d = Hs[i + (size_t)i * (kk + 1)];
+    if (std::abs(d) == 0.0) return SK_ERR_SINGULAR;
+    ys[i] = acc / d;
+  }
+  // z = beta rho_s e_1 - (Hbar - sigma_s I~) y_s, from the original matrix
+  for (int r = 0; r <= kk; ++r) {
+    cd acc = (r == 0) ? g[0] : cd(0.0);
+    for (int c = 0; c < kk; ++c) acc -= (h(r, c) - (r == c ? sig(seed) : cd(0.0))) * ys[c];
+    z[r] = acc;
+  }
+  for (int r = 0; r < kk; ++r) Y[(size_t)seed * kk + r] = ys[r];
+  std::vector<cd> rho_new(N, cd(0.0));
+  rho_new[seed] = 1.0;
+  for (int i = 0; i < N; ++i) {
+    if (i == seed) continue;
+    const int m1 = kk + 1;
+    std::vector<cd> A((size_t)m1 * m1), rhs(m1, cd(0.0));
+    for (int c = 0; c < kk; ++c)
+      for (int r = 0; r <= kk; ++r) A[r + (size_t)c * m1] = h(r, c) - (r == c ? sig(i) : cd(0.0));
+    for (int r = 0; r <= kk; ++r) A[r + (size_t)kk * m1] = z[r];
+    rhs[0] = beta * rho[i];
+    if (!dense::lu_solve(m1, A, rhs, 1)) return SK_ERR_SINGULAR;
+    for (int r = 0; r < kk; ++r) Y[(size_t)i * kk + r] = rhs[r];
+    rho_new[i] = rhs[kk];
+  }
+  rho = rho_new;
+  return SK_OK;
+}
+
+int gmres_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, double2* x, sk_stats* stats,
+               void* ws, hipStream_t s) {
+  using cd = dense::cd;
+  const int64_t n = 12 * volume_of(op);
+  const int k = p->k, m = p->m, N = p->npoles;
+  const double2* R = (const double2*)p->R;
+  const double2* Lv = (const double2*)p->L;
+  Carver c;
+  c.base = (char*)ws;
+  SignWs sw;
+  carve_sign(c, sw, n, p);
+  KrylovWs<double2>& w = sw.w64;
+  double2* X = (double2*)p->X_shift;
+  PoleSet ps;
+  SK_TRY(fill_poles(ps, N, p->sigma, p->omega));
+  int seed = p->seed;
+  if (seed < 0) {
+    seed = 0;
+    for (int i = 1; i < N; ++i)
+      if (cabs2(ps.sigma[i]) < cabs2(ps.sigma[seed])) seed = i;
+  }
+  const ArnoldiDev a = arn_of(w, k);
+  const int cs = ts_counter_stride(n);
+  SK_LAUNCH(launch_init_state(w.st, w.rho, N, w.counter, kCounterSlots * cs, s));
+  SK_LAUNCH(launch_fill_zero((double*)w.H, (int64_t)(k + 1) * k * 2, s));
+  SK_LAUNCH(launch_fill_value(w.scale, k + 2, 1.0, s));
+  if (X) SK_LAUNCH(launch_fill_zero((double*)X, (int64_t)N * n * 2, s));
+  const TsEpiArgs e0 = epi_of(EPI_NONE, a);
+  TsEpiArgs eb = epi_of(EPI_BETA, a);
+  eb.dst_scalar = &w.st->beta;
+  eb.dst_scale = w.scale + k + 1;
+  if (m > 0) {
+    TsEpiArgs ed = epi_of(EPI_DEFL, a);
+    ed.out = w.dc;
+    ed.out2 = w.dc2;
+    ed.F = (const double2*)p->F;
+    ed.dst_scalar = &w.st->leak;
+    SK_LAUNCH((ts_dot<double2, double2>(Lv, n, m, b, n, false, ed, w.partial, w.counter + 4 * cs, nullptr, s)));
+    SK_LAUNCH((ts_gemv<double2>(R, n, m, w.dc2, x, n, false, 0, e0, nullptr, nullptr, nullptr, nullptr, s)));
+  } else {
+    SK_LAUNCH(launch_fill_zero((double*)x, n * 2, s));
+  }
+  SK_LAUNCH((ts_update<double2, double2, double2>(m > 0 ? R : nullptr, n, m, w.dc, nullptr, b, w.W, n, 2, eb,
+                                                  w.partial, w.counter + 5 * cs, nullptr, s)));
+  CycleState hs;
+  SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  SK_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->cycles = stats->cycles_c64 = stats->matvecs = stats->converged = stats->breakdown = 0;
+    stats->final_update_norm = stats->x_norm = 0.0;
+    stats->resid_checked = stats->resid_ok = 0;
+  }
+  if (hs.nonfinite || !std::isfinite(hs.beta)) {
+    set_error("source contains non-finite values");
+    return SK_ERR_NAN;
+  }
+  if (hs.beta == 0.0) {
+    if (stats) stats->converged = 1;
+    return SK_OK;
+  }
+  std::vector<cd> rho(N, cd(1.0)), Hh, Y, z;
+  std::vector<double2> hbuf((size_t)(k + 1) * k), ubuf(k + 1), ybuf((size_t)N * k), zbuf(k + 1);
+  int small = 0, status = SK_ERR_NOCONV;
+  double first = 0.0;
+  for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
+    SK_TRY(enqueue_arnoldi<double2>(op, w, n, k, 0, s));
+    SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipMemcpyAsync(hbuf.data(), w.H, hbuf.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipStreamSynchronize(s));
+    if (hs.nonfinite) {
+      set_error("non-finite value in cycle %d", cyc + 1);
+      status = SK_ERR_NAN;
+      break;
+    }
+    const int kk = hs.kdone;
+    Hh.assign(hbuf.size(), cd(0.0));
+    for (size_t e = 0; e < hbuf.size(); ++e) Hh[e] = cd(hbuf[e].x, hbuf[e].y);
+    const int rc = gmres_small(kk, Hh, k + 1, hs.beta, rho, ps, seed, hs.breakdown != 0, Y, z);
+    if (rc != SK_OK) {
+      set_error("GMRES-LR: singular small system in cycle %d", cyc + 1);
+      status = rc;
+      break;
+    }
+    double un2 = 0.0;
+    for (int r = 0; r < kk; ++r) {
+      cd u = 0.0;
+      for (int i = 0; i < N; ++i) u += cd(ps.omega[i].x, ps.omega[i].y) * Y[(size_t)i * kk + r];
+      ubuf[r] = make_double2(u.real(), u.imag());
+      un2 += std::norm(u);
+    }
+    const double un = std::sqrt(un2);
+    for (int i = 0; i < N; ++i)
+      for (int r = 0; r < kk; ++r) ybuf[(size_t)i * k + r] = make_double2(Y[(size_t)i * kk + r].real(), Y[(size_t)i * kk + r].imag());
+    for (int r = 0; r <= kk; ++r) zbuf[r] = make_double2(z[r].real(), z[r].imag());
+    SK_HIP(hipMemcpyAsync(w.ucoef, ubuf.data(), kk * sizeof(double2), hipMemcpyHostToDevice, s));
+    if (X) SK_HIP(hipMemcpyAsync(w.ycoef, ybuf.data(), (size_t)N * k * sizeof(double2), hipMemcpyHostToDevice, s));
+    SK_HIP(hipMemcpyAsync(sw.zdev, zbuf.data(), (kk + 1) * sizeof(double2), hipMemcpyHostToDevice, s));
+    // x += V_kk u (and X_i += V_kk y_i), ||x||^2
+    TsEpiArgs ex = epi_of(EPI_XNORM, a);
+    ex.dst_scalar = &w.st->xnorm2;
+    SK_LAUNCH((ts_gemv<double2>(w.W, n, kk, w.ucoef, x, n, true, 2, ex, w.partial, w.counter + 6 * cs, nullptr,
+                                nullptr, s)));
+    if (X) SK_LAUNCH((ts_multi_gemv<double2>(w.W, n, kk, w.ycoef, k, N, X, n, nullptr, s)));
+    const bool done_exact = hs.breakdown != 0;
+    if (!done_exact) {
+      // r = (I - P) V_{kk+1} z, the next cycle's start vector (normalised by its first step)
+      SK_LAUNCH((ts_gemv<double2>(w.W, n, kk + 1, sw.zdev, sw.rnext, n, false, 0, e0, nullptr, nullptr, nullptr,
+                                  nullptr, s)));
+      if (m > 0 && p->project_each_cycle) {
+        TsEpiArgs el = epi_of(EPI_DEFL, a);
+        el.out = w.dc2;
+        el.dst_scalar = &w.st->leak;
+        SK_LAUNCH((ts_dot<double2, double2>(Lv, n, m, sw.rnext, n, false, el, w.partial, w.counter + 4 * cs,
+                                            nullptr, s)));
+        SK_LAUNCH((ts_update<double2, double2, double2>(R, n, m, w.dc2, nullptr, sw.rnext, w.W, n, 0, e0,
+                                                        w.partial, w.counter + 5 * cs, nullptr, s)));
+      } else {
+        SK_LAUNCH((ts_scale<double2, double2>(sw.rnext, w.W, n, nullptr, 1.0, s)));
+      }
+    }
+    SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipStreamSynchronize(s));
+    if (stats) {
+      stats->cycles = cyc + 1;
+      stats->matvecs += kk;
+      stats->final_update_norm = un;
+      stats->x_norm = std::sqrt(hs.xnorm2);
+      if (cyc < stats->hist_cap) {
+        if (stats->hist_update) stats->hist_update[cyc] = un;
+        if (stats->hist_beta) stats->hist_beta[cyc] = hs.beta;
+        if (stats->hist_leak) stats->hist_leak[cyc] = hs.leak;
+        if (stats->hist_rho)
+          for (int i = 0; i < N; ++i) stats->hist_rho[(size_t)cyc * N + i] = std::abs(rho[i]);
+      }
+    }
+    if (done_exact) {
+      if (stats) stats->breakdown = 1;
+      status = SK_OK;
+      break;
+    }
+    if (!std::isfinite(un) || hs.nonfinite) {
+      set_error("non-finite value in cycle %d (restarted GMRES diverged)", cyc + 1);
+      status = SK_ERR_NAN;
+      break;
+    }
+    small = (un <= p->tol * std::sqrt(hs.xnorm2)) ? small + 1 : 0;
+    if (small >= 2) {
+      status = SK_OK;
+      break;
+    }
+    if (cyc == 0) first = un;
+    else if (un > kDivergeFactor * first) {
+      set_error("restarted GMRES diverged (cycle %d, update %.3e): try another restart length", cyc + 1, un);
+      if (stats) stats->converged = 0;
+      return SK_ERR_NOCONV;
+    }
+    // rho lives on the host; the device copy is only for the statistics of FOM
+  }
+  if (stats) stats->converged = (status == SK_OK);
+  if (status == SK_ERR_NOCONV) set_error("not converged after %d cycles", p->max_cycles);
   return status;
 }
 
@@ -661,11 +999,18 @@ int sign_apply(const sk_operator* op, const sk_sign_params* p, const double* b, 
     return SK_ERR_WORKSPACE;
   }
   SK_CHECK(!overlap(ws, need, x, n * 16) && !overlap(ws, need, b, n * 16), "workspace overlaps b or x");
-  return sign_impl(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int st = p->method == SK_METHOD_GMRES
+                     ? gmres_impl(op, p, (const double2*)b, (double2*)x, stats, ws, stream)
+                     : sign_impl(op, p, (const double2*)b, (double2*)x, stats, ws, stream);
+  if (stats) stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
 }
 
 size_t sign_apply_backward_workspace_bytes(const sk_operator* op, const sk_sign_params* p) {
-  if (!op || !p || volume_of(op) <= 0 || p->m != 0 || p->precision != SK_PREC_FP64) return 0;
+  if (!op || !p || volume_of(op) <= 0 || p->m != 0 || p->precision != SK_PREC_FP64 ||
+      p->method != SK_METHOD_FOM)
+    return 0;
   char msg[256];
   if (!params_ok(p, msg, sizeof msg)) return 0;
   const int64_t n = 12 * volume_of(op);
@@ -688,6 +1033,7 @@ int sign_apply_backward(const sk_operator* op, const sk_sign_params* p, const do
   SK_CHECK(params_ok(p, msg, sizeof msg), "%s", msg);
   SK_CHECK(p->m == 0, "the gradient is defined without deflation (m must be 0)");
   SK_CHECK(p->precision == SK_PREC_FP64, "the gradient runs in complex double");
+  SK_CHECK(p->method == SK_METHOD_FOM, "the gradient uses the FOM per-shift solutions");
   SK_CHECK(b && eta && grad_theta && grad_mu && ws, "NULL argument");
   const int64_t n = 12 * volume_of(op), V = volume_of(op);
   const size_t need = sign_apply_backward_workspace_bytes(op, p);

@@ -459,3 +459,188 @@ def test_exact_mu_derivative_of_hw(anti):
     U0 = U.copy()
     U0[:, :3] = 0
     assert abs(dirac.hw_csr(U0, dims, 0.25, mu, anti, d_mu=True) - dH).max() == 0.0
+
+
+# ---------------------------------------------------------------- direct projection methods
+def test_direct_arnoldi_full_space_is_exact(small_hw):
+    """eq. (direct) with the whole space (k = n, 2^4) is sign(A) b exactly;
+    with deflation too (the deflated part is x_P exactly)."""
+    from oracle import direct
+    A, _, _ = small_hw
+    n = A.shape[0]
+    b = si.gaussian_source(n, 60)
+    ex = signfun.sign_schur(A) @ b
+    x, info = direct.arnoldi_direct(lambda v: A @ v, b, n)
+    assert rel(x, ex) < 1e-12
+    R, L, lam, F = deflation.lr_dense(A, 20)
+    # (I - P) b lies in an invariant subspace of dimension n - 20
+    x, info = direct.arnoldi_direct(lambda v: A @ v, b, n - 20, R, L, F)
+    assert rel(x, ex) < 1e-11
+
+
+def test_two_sided_lanczos_relations_and_hermitian_limit(small_hw):
+    from oracle import direct
+    A, dims, U = small_hw
+    n = A.shape[0]
+    b = si.gaussian_source(n, 61)
+    v1 = b / np.linalg.norm(b)
+    w1 = si.gaussian_source(n, 62)
+    V, W, T, kk = direct.two_sided_lanczos(lambda v: A @ v, lambda v: A.conj().T @ v, v1, w1, 15)
+    assert kk == 15
+    assert np.linalg.norm(W.conj().T @ V - np.eye(16)) < 1e-10          # biorthogonal
+    assert np.linalg.norm(A @ V[:, :15] - V @ T) < 1e-12 * np.linalg.norm(A)
+    assert np.linalg.norm(np.triu(T[:15, :15], 2)) == 0 and np.linalg.norm(np.tril(T, -2)) == 0
+    # mu = 0, w_1 = v_1: Hermitian Lanczos, which is Arnoldi (unique H_k)
+    A0 = dirac.hw_dense(U, dims, 0.25, 0.0)
+    V, W, T, kk = direct.two_sided_lanczos(lambda v: A0 @ v, lambda v: A0.conj().T @ v, v1, v1, 25)
+    Va, H, ka = krylov.arnoldi(lambda v: A0 @ v, v1, 25)
+    assert np.abs(T - H).max() < 1e-13 and np.abs(V - Va).max() < 1e-12
+
+
+def test_lanczos_left_space_avoids_the_deflated_left_subspace(small_hw):
+    """With LR deflation the left start (I - L R^H) v_1 keeps R^H W = 0
+    (A^H maps ker R^H into itself), the right space keeps L^H V = 0."""
+    from oracle import direct
+    A, _, _ = small_hw
+    n = A.shape[0]
+    R, L, lam, F = deflation.lr_dense(A, 12)
+    b = si.gaussian_source(n, 63)
+    x, info = direct.lanczos_direct(lambda v: A @ v, lambda v: A.conj().T @ v, b, 20, R, L, F)
+    assert np.linalg.norm(R.conj().T @ info["W"]) < 1e-10
+    assert np.linalg.norm(L.conj().T @ info["V"]) < 1e-10
+    assert abs(np.vdot(info["W"][:, 0], info["V"][:, 0]) - 1) < 1e-13
+
+
+def test_direct_methods_on_a_plane_wave():
+    """Free field: both direct methods stop after 2 steps with the exact
+    momentum-space sign."""
+    from oracle import direct
+    dims = (4, 4, 4, 4)
+    V = 256
+    A = dirac.hw_csr(si.unit_links(dims), dims, 0.25, 0.3)
+    AH = dirac.hw_csr(si.unit_links(dims), dims, 0.25, -0.3)
+    chi = si.gaussian_source(12, 15).reshape(4, 3)
+    s = np.arange(V)
+    x_, z_, t_ = s % 4, (s // 16) % 4, s // 64
+    ph = np.exp(1j * (2 * np.pi / 4 * x_ + np.pi * z_ + (np.pi / 4 + np.pi / 2) * t_))
+    b = (ph[:, None, None] * chi[None]).reshape(-1)
+    ref = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: np.sign(l.real))
+    xa, ia = direct.arnoldi_direct(lambda v: A @ v, b, 10)
+    xl, il = direct.lanczos_direct(lambda v: A @ v, lambda v: AH @ v, b, 10)
+    assert ia["k"] == 2 and il["k"] == 2
+    assert rel(xa, ref) < 1e-12 and rel(xl, ref) < 1e-12
+
+
+def test_newton_sign_stops_at_rounding_level():
+    """Roberts' iteration on an ill-conditioned matrix: the change levels
+    off near roundoff; the iteration still returns sign(A) (checked against
+    the sorted-Schur sign)."""
+    rng = np.random.default_rng(5)
+    n = 40
+    Q = np.linalg.qr(rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n)))[0]
+    lam = np.concatenate([rng.uniform(0.01, 2, n // 2), -rng.uniform(0.01, 2, n // 2)]) + 1j * rng.normal(size=n)
+    T = np.diag(lam) + np.triu(rng.normal(size=(n, n)) * 0.5, 1)
+    A = Q @ T @ Q.conj().T
+    S = signfun.sign_newton(A)
+    assert rel(S, signfun.sign_schur(A)) < 1e-8
+    assert np.linalg.norm(S @ S - np.eye(n)) / np.sqrt(n) < 1e-8
+
+
+# ---------------------------------------------------------------- overlap operator
+def test_overlap_operator_identities(small_hw):
+    """With the exact sign: Ginsparg-Wilson relation of the massless operator
+    (gamma5 D + D gamma5 = D gamma5 D, which holds for any S with S^2 = I and
+    fails if gamma5 is misplaced), gamma5-hermiticity gamma5 D(mu) gamma5 =
+    D(-mu)^H, and the mass term D(m) = (1 - m/2) D(0) + m."""
+    from oracle import overlap
+    A, dims, U = small_hw
+    n = A.shape[0]
+    S = signfun.sign_schur(A)
+    D = overlap.overlap_matrix(S)
+    G5 = overlap.gamma5_matrix(n)
+    assert np.linalg.norm(G5 @ D + D @ G5 - D @ G5 @ D) / np.linalg.norm(D) < 1e-12
+    Sm = signfun.sign_schur(dirac.hw_dense(U, dims, 0.25, -0.3))
+    assert np.linalg.norm(G5 @ D @ G5 - overlap.overlap_matrix(Sm).conj().T) / np.linalg.norm(D) < 1e-12
+    m = 0.2
+    assert np.linalg.norm(overlap.overlap_matrix(S, m) - ((1 - m / 2) * D + m * np.eye(n))) < 1e-12
+    b = si.gaussian_source(n, 70)
+    assert rel(overlap.overlap_apply(lambda v: S @ v, b, m), overlap.overlap_matrix(S, m) @ b) < 1e-14
+
+
+def test_overlap_free_field_closed_form():
+    """Free field: D(0) b = b + gamma5 sign(H(p)) b in momentum space."""
+    from oracle import overlap
+    dims = (2, 2, 2, 4)
+    b = si.gaussian_source(12 * 32, 71)
+    sb = dirac.free_field_function(b, dims, 0.25, 0.3, lambda l: np.sign(l.real))
+    ref = b + overlap.gamma5_vec(sb)
+    A = dirac.hw_dense(si.unit_links(dims), dims, 0.25, 0.3)
+    S = signfun.sign_schur(A)
+    assert rel(overlap.overlap_apply(lambda v: S @ v, b), ref) < 1e-12
+
+
+def test_sign_map_matrix_columns_are_xstar(small_hw):
+    from oracle import overlap
+    A, _, _ = small_hw
+    n = A.shape[0]
+    R, L, lam, F = deflation.lr_dense(A, 8)
+    sig, om = rational.kl_first_order(5, 0.9)
+    G = overlap.sign_map_matrix(A, sig, om, R, L, F)
+    b = si.gaussian_source(n, 72)
+    assert rel(G @ b, xstar.xstar_dense(A, b, sig, om, R, L, F)) < 1e-12
+
+
+# ---------------------------------------------------------------- GMRES-LR
+def test_gmres_seed_minimises_its_residual_and_others_stay_collinear():
+    """One GMRES-LR cycle: the seed iterate minimises ||b - (A - sigma_s) x||
+    over the Krylov space (checked by a least-squares solve on the explicit
+    basis), and every other shifted residual is a multiple of the seed's."""
+    from oracle import gmres
+    dims = (2, 2, 3, 4)
+    V = 48
+    A = dirac.hw_csr(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    sig, om = rational.kl_first_order(5, 0.9)
+    k = 12
+    x, info = gmres.restarted_gmres_lr(lambda v: A @ v, b, sig, om, k, max_cycles=1,
+                                       keep_shift_solutions=True)
+    X, s = info["X"], info["seed"]
+    Vb, H, kk = krylov.arnoldi(lambda v: A @ v, b / np.linalg.norm(b), k)
+    M = A @ Vb[:, :k] - sig[s] * Vb[:, :k]
+    y = np.linalg.lstsq(M, b, rcond=None)[0]
+    assert rel(X[s], Vb[:, :k] @ y) < 1e-10
+    rs = b - (A @ X[s] - sig[s] * X[s])
+    for i in range(len(sig)):
+        ri = b - (A @ X[i] - sig[i] * X[i])
+        off = ri - np.vdot(rs, ri) / np.vdot(rs, rs) * rs
+        assert np.linalg.norm(off) < 1e-10 * np.linalg.norm(b)
+        assert abs(np.vdot(rs, ri) / np.vdot(rs, rs) - info["rho"][i]) < 1e-9 * max(1, abs(info["rho"][i]))
+
+
+@pytest.mark.parametrize("k,m", [(20, 0), (40, 0), (12, 10)])
+def test_gmres_lr_converges_to_xstar(k, m):
+    from oracle import gmres
+    dims = (2, 2, 3, 4)
+    V = 48
+    Ad = dirac.hw_dense(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    sig, om = rational.kl_first_order(5, 0.9)
+    R = L = F = None
+    if m:
+        R, L, lam, F = deflation.lr_dense(Ad, m)
+    ref = xstar.xstar_dense(Ad, b, sig, om, R, L, F)
+    x, info = gmres.restarted_gmres_lr(lambda v: Ad @ v, b, sig, om, k, R, L, F, tol_update=1e-12,
+                                       max_cycles=500)
+    assert info["converged"] and rel(x, ref) < 1e-10
+
+
+def test_gmres_lr_short_cycle_divergence_is_reported():
+    from oracle import gmres
+    dims = (2, 2, 3, 4)
+    V = 48
+    A = dirac.hw_csr(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    sig, om = rational.kl_first_order(5, 0.9)
+    with np.errstate(all="ignore"):
+        x, info = gmres.restarted_gmres_lr(lambda v: A @ v, b, sig, om, 8, max_cycles=2000)
+    assert not info["converged"]
