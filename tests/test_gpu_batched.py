@@ -292,3 +292,73 @@ def test_deflated_lattices_whose_row_blocking_is_not_monotone():
         d = float((r.x - s_.x).norm() / s_.x.norm())
         print(f"batched vs single: {d:.2e}, cycles {r.cycles} vs {s_.cycles}")
         assert r.converged and d <= 1e-9
+
+
+def test_batched_84_source_workload():
+    """The batched configuration itself: 12 spin-colour point sources at site 0
+    and 16 Z2 sources on each of the 6^4 (eps 0.5, m 10, k 40), 8^4 (eps 0.6,
+    m 20, k 50) and 10^4 (eps 0.7, m 40, k 60) fields at mu = 0.3, 16 poles at
+    each lattice's scale, GPU deflation, mixed precision switching to complex
+    float at a relative update of 1e-2, all 84 systems in one batch.  Every
+    system against the same source solved alone in complex double (itself
+    pinned to the oracle below), and each lattice's Gaussian source, solved
+    in a batch of its own with the same settings, against the oracle's full
+    x*."""
+    import json
+    import os
+    import torch
+    from paper_0910_2927_amd import api
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    mu = 0.3
+    tol = 1e-10
+    lattices, systems, bs = [], [], []
+    for name in ("c6", "c2", "c3"):
+        cfg = CONFIGS[name]
+        U = si.gauge_links(cfg.dims, cfg.eps, si.seed_for(cfg.L, "gauge"))
+        op = make_op(U, cfg.dims, cfg.kappa, mu, with_c64=True)
+        announce(f"eigensolve {name} for the batch")
+        R, Lv, F, lam, st = api.deflation_eigensolve(op, cfg.m, nev_extra=16, tol=1e-12)
+        sig, om = api.kl_poles(cfg.s, cfg.scales[mu])
+        srcs = [si.point_source(cfg.n, 0, sc // 3, sc % 3) for sc in range(12)]
+        srcs += [si.z2_source(cfg.n, si.seed_for(cfg.L, "z2", i)) for i in range(16)]
+        lt = dict(cfg=cfg, op=op, defl=(R, Lv, F), sig=sig, om=om, srcs=srcs)
+        lattices.append(lt)
+        for b in srcs:
+            systems.append({"op": op, "defl": (R, Lv, F), "k": cfg.k, "sigma": sig, "omega": om})
+            bs.append(to_dev(b, cfg.V))
+    assert len(systems) == 84
+    announce("sign_apply_batched 84 systems, mixed, switch 1e-2")
+    solver = api.BatchedSignSolver(systems, lattices[0]["sig"], lattices[0]["om"], lattices[0]["cfg"].k,
+                                   tol=tol, max_cycles=400, precision="mixed", mixed_switch=1e-2)
+    res = solver(bs)
+    assert all(r.converged for r in res)
+    assert max(r.cycles_c64 for r in res) > 0
+    z = 0
+    worst = []
+    for lt in lattices:
+        cfg = lt["cfg"]
+        R, Lv, F = lt["defl"]
+        single = api.SignSolver(lt["op"], lt["sig"], lt["om"], cfg.k, tol=tol, max_cycles=400, R=R, Lv=Lv, F=F)
+        errs = []
+        for b in bs[z:z + 28]:
+            r1 = single(b)
+            errs.append(float(torch.linalg.vector_norm(res[z + len(errs)].x - r1.x)
+                              / torch.linalg.vector_norm(r1.x)))
+        z += 28
+        worst.append(max(errs))
+        # the Gaussian source of the lattice against the oracle's full x*
+        g = json.load(open(os.path.join(golden, f"{cfg.name}_mu{mu:g}.json")))
+        bg = si.gaussian_source(cfg.n, si.seed_for(cfg.L, "b"))
+        announce(f"batched Gaussian source {cfg.name}")
+        rg = api.BatchedSignSolver([{"op": lt["op"], "defl": lt["defl"], "k": cfg.k, "sigma": lt["sig"],
+                                     "omega": lt["om"]}], lt["sig"], lt["om"], cfg.k, tol=tol, max_cycles=400,
+                                   precision="mixed", mixed_switch=1e-2)([to_dev(bg, cfg.V)])[0]
+        xg = from_dev(rg.x, cfg.V)
+        full = os.path.join(golden, f"{cfg.name}_mu{mu:g}_x.npy")
+        if os.path.exists(full):
+            eg = rel(xg, np.load(full))
+        else:
+            eg = rel(xg[np.array(g["sample_index"])], np.array(g["x_re"]) + 1j * np.array(g["x_im"]))
+        print(f"{cfg.name}: batch vs single complex double max {max(errs):.2e}; Gaussian vs oracle {eg:.2e}")
+        assert eg <= 1e-8
+    assert max(worst) <= 1e-8
