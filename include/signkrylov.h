@@ -164,6 +164,21 @@ int deflate_project(int m, int64_t n, const double* R, const double* L, const do
                     const double* in, double* r_out, double* xp_out, double* coeff,
                     void* ws, size_t ws_bytes, hipStream_t stream);
 
+/*
+ * deflate_project without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * deflate_project; the scratch lives in a 7 MiB device array inside the
+ * library, one per GPU, held until the process ends.  Limits: m <= 128 and
+ * n <= 12 * 16^4 (larger sizes return SK_ERR_ARG before any launch).  The
+ * call allocates nothing.  Every call on one GPU uses that GPU's array:
+ * calls that overlap in time on one GPU (other streams, other threads)
+ * race and must be serialised by the caller.
+ */
+int deflate_project_noalloc(int m, int64_t n, const double* R, const double* L, const double* F,
+                            const double* in, double* r_out, double* xp_out, double* coeff,
+                            hipStream_t stream);
+
 typedef struct {
   int32_t npoles;           /* N first-order poles of eq. (g) */
   const double* sigma;      /* host, N complex (re, im) */

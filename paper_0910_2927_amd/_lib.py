@@ -117,6 +117,8 @@ SIGNATURES = [
     ("deflate_project", C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_size_t, C.c_void_p]),
+    ("deflate_project_noalloc", C.c_int, [C.c_int, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("sign_apply_workspace_bytes", C.c_size_t, [C.POINTER(SkOperator), C.POINTER(SkSignParams)]),
     ("sign_apply", C.c_int, [C.POINTER(SkOperator), C.POINTER(SkSignParams), C.c_void_p,
                              C.c_void_p, C.POINTER(SkStats), C.c_void_p, C.c_size_t, C.c_void_p]),

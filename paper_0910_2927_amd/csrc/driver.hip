@@ -289,36 +289,31 @@ int multishift_fom_restart(int k, int64_t n, sk_dtype dtype, const double* H, in
                             (double2*)x, (double2*)X_shift, upd_norm, ws, stream);
 }
 
-// ------------------------------------------------------------------ deflate_project
-size_t deflate_project_workspace_bytes(int m, int64_t n) {
-  if (m < 1 || m > kMaxDefl || n < 1) return 0;
-  Carver c;
-  c.take<double2>(ts_partial_entries(n, m));
-  c.take<unsigned>(2 * ts_counter_stride(n));
-  c.take<double2>(m);
-  c.take<CycleState>(1);
-  return c.off;
-}
+}  // extern "C"
 
-int deflate_project(int m, int64_t n, const double* R, const double* L, const double* F,
-                    const double* in, double* r_out, double* xp_out, double* coeff, void* ws,
-                    size_t ws_bytes, hipStream_t s) {
+namespace sk {
+int deflate_project_check(int m, int64_t n, const double* R, const double* L, const double* F,
+                          const double* in, const double* r_out, const double* xp_out, const double* coeff) {
   SK_CHECK(m >= 1 && m <= kMaxDefl, "m = %d outside [1, %d]", m, kMaxDefl);
   SK_CHECK(n >= 1, "n must be positive");
-  SK_CHECK(R && L && in && r_out && coeff && ws, "NULL argument");
+  SK_CHECK(R && L && in && r_out && coeff, "NULL argument");
   SK_CHECK(r_out == in || !overlap(in, n * 16, r_out, n * 16), "r_out partially overlaps in");
   if (xp_out) {
     SK_CHECK(F != nullptr, "xp_out requested without F");
     SK_CHECK(!overlap(xp_out, n * 16, in, n * 16) && !overlap(xp_out, n * 16, r_out, n * 16),
              "xp_out overlaps in/r_out");
   }
-  const size_t need = deflate_project_workspace_bytes(m, n);
-  if (ws_bytes < need) {
-    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
-    return SK_ERR_WORKSPACE;
-  }
+  return SK_OK;
+}
+
+// The projection kernels with their scratch (partial sums, counters, F c,
+// state) carved from `scratch`, at least deflate_project_workspace_bytes(m, n).
+// The counters are cleared by a kernel at the start of every call.
+int deflate_project_run(int m, int64_t n, const double* R, const double* L, const double* F,
+                        const double* in, double* r_out, double* xp_out, double* coeff, void* scratch,
+                        hipStream_t s) {
   Carver c;
-  c.base = (char*)ws;
+  c.base = (char*)scratch;
   double2* partial = c.take<double2>(ts_partial_entries(n, m));
   const int cs = ts_counter_stride(n);
   unsigned* counter = c.take<unsigned>(2 * cs);
@@ -344,6 +339,33 @@ int deflate_project(int m, int64_t n, const double* R, const double* L, const do
                                                   nullptr, (const double2*)in, (double2*)r_out, n, 0,
                                                   e1, partial, counter + cs, nullptr, s)));
   return SK_OK;
+}
+}  // namespace sk
+
+extern "C" {
+
+// ------------------------------------------------------------------ deflate_project
+size_t deflate_project_workspace_bytes(int m, int64_t n) {
+  if (m < 1 || m > kMaxDefl || n < 1) return 0;
+  Carver c;
+  c.take<double2>(ts_partial_entries(n, m));
+  c.take<unsigned>(2 * ts_counter_stride(n));
+  c.take<double2>(m);
+  c.take<CycleState>(1);
+  return c.off;
+}
+
+int deflate_project(int m, int64_t n, const double* R, const double* L, const double* F,
+                    const double* in, double* r_out, double* xp_out, double* coeff, void* ws,
+                    size_t ws_bytes, hipStream_t s) {
+  SK_TRY(deflate_project_check(m, n, R, L, F, in, r_out, xp_out, coeff));
+  SK_CHECK(ws != nullptr, "NULL argument");
+  const size_t need = deflate_project_workspace_bytes(m, n);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu bytes", ws_bytes, need);
+    return SK_ERR_WORKSPACE;
+  }
+  return deflate_project_run(m, n, R, L, F, in, r_out, xp_out, coeff, ws, s);
 }
 
 }  // extern "C"

@@ -199,6 +199,14 @@ int grad_blocks(int64_t V);
 hipError_t launch_grad(const sk_operator* op, const PoleSet& ps, const double2* X, const double2* Z,
                        double* grad, double* mu_part, hipStream_t s);
 
+// deflate_project's argument checks and its launches on a given scratch area
+// (driver.hip), shared by the workspace and the workspace-free entry points.
+int deflate_project_check(int m, int64_t n, const double* R, const double* L, const double* F,
+                          const double* in, const double* r_out, const double* xp_out, const double* coeff);
+int deflate_project_run(int m, int64_t n, const double* R, const double* L, const double* F,
+                        const double* in, double* r_out, double* xp_out, double* coeff, void* scratch,
+                        hipStream_t s);
+
 hipError_t launch_zero_counters(unsigned* counter, int n, hipStream_t s);
 hipError_t launch_fill_zero(double* p, int64_t count, hipStream_t s);
 hipError_t launch_fill_value(double* p, int64_t count, double v, hipStream_t s);
