@@ -6,7 +6,10 @@
 
 #include <chrono>
 #include <cstring>
+#include <list>
+#include <memory>
 #include <mutex>
+#include <string>
 #include <vector>
 
 namespace sk {
@@ -529,6 +532,66 @@ struct CycleGraphs {
   }
 };
 
+// Instantiated cycle graphs outlive the call: a later call whose captured
+// arguments are the same (operator, poles and parameters, x, X and the
+// workspace -- every address a cycle's kernels use derives from these)
+// replays them without capturing again.  Least recently used first out;
+// the cache is never torn down at process exit (the HIP runtime may be gone).
+constexpr size_t kGraphCacheSize = 8;
+
+struct GraphCache {
+  std::mutex mu;
+  std::list<std::pair<std::string, std::shared_ptr<CycleGraphs>>> lru;
+};
+
+GraphCache& graph_cache() {
+  static GraphCache* c = new GraphCache();
+  return *c;
+}
+
+template <typename T> void put_bytes(std::string& k, const T& v) {
+  k.append(reinterpret_cast<const char*>(&v), sizeof(T));
+}
+
+std::string graph_key(const sk_operator* op, const sk_sign_params* p, const void* x, const void* X,
+                      const void* ws) {
+  std::string k;
+  for (int i = 0; i < 4; ++i) put_bytes(k, op->dims[i]);
+  put_bytes(k, op->t_antiperiodic);
+  put_bytes(k, op->kappa);
+  put_bytes(k, op->mu);
+  put_bytes(k, op->links);
+  put_bytes(k, op->links_c64);
+  put_bytes(k, p->npoles);
+  k.append(reinterpret_cast<const char*>(p->sigma), 16 * (size_t)p->npoles);
+  k.append(reinterpret_cast<const char*>(p->omega), 16 * (size_t)p->npoles);
+  put_bytes(k, p->k);
+  put_bytes(k, p->m);
+  put_bytes(k, p->R);
+  put_bytes(k, p->L);
+  put_bytes(k, p->F);
+  put_bytes(k, p->project_each_cycle);
+  put_bytes(k, p->precision);
+  put_bytes(k, p->X_shift);
+  put_bytes(k, x);
+  put_bytes(k, X);
+  put_bytes(k, ws);
+  return k;
+}
+
+std::shared_ptr<CycleGraphs> graphs_for(const std::string& key) {
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto it = c.lru.begin(); it != c.lru.end(); ++it)
+    if (it->first == key) {
+      c.lru.splice(c.lru.begin(), c.lru, it);
+      return c.lru.front().second;
+    }
+  c.lru.emplace_front(key, std::make_shared<CycleGraphs>());
+  while (c.lru.size() > kGraphCacheSize) c.lru.pop_back();
+  return c.lru.front().second;
+}
+
 int enqueue_cycle_kind(int kind, const CycleArgs& ca, SignWs& sw) {
   if (kind == 0) return enqueue_cycle<double2, double2>(ca, sw);
   if (kind == 1) return enqueue_cycle<double2, float2>(ca, sw);
@@ -643,8 +706,10 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
     tm.s = s;
   }
   CycleArgs ca{op, p, n, &ps, x, X, &tm, s};
-  CycleGraphs graphs;
   const bool use_graph = !tm.on();   // per-kernel timing needs plain launches
+  std::shared_ptr<CycleGraphs> gptr = use_graph ? graphs_for(graph_key(op, p, x, X, ws))
+                                                : std::make_shared<CycleGraphs>();
+  CycleGraphs& graphs = *gptr;
   int small = 0, status = SK_ERR_NOCONV;
   double first_upd = 0.0;
   bool diverged = false;

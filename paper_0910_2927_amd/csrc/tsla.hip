@@ -347,6 +347,11 @@ __global__ __launch_bounds__(NT) void k_ts_gemv(const TQ* __restrict__ Q, int64_
   finish(epi, partial, 1, 1, counter);
 }
 
+// X_i += sum_j Q_j C[i*ldc + j] for the outputs i of this block row
+// (grid.y picks kMgOut consecutive outputs): one row per thread, kMgOut
+// accumulators, 8 basis loads in flight; the basis is read once per group
+// of outputs, which keeps the per-thread chain short.
+constexpr int kMgOut = 8;
 template <typename TQ>
 __global__ __launch_bounds__(NT) void k_ts_multi_gemv(const TQ* __restrict__ Q, int64_t ldq, int p,
                                                       const double2* __restrict__ C, int ldc,
@@ -354,32 +359,37 @@ __global__ __launch_bounds__(NT) void k_ts_multi_gemv(const TQ* __restrict__ Q, 
                                                       const int* pdev) {
   if (pdev) p = min(p, *pdev);
   const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (r >= n) return;
-  for (int o0 = 0; o0 < nout; o0 += 16) {
-    double2 acc[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc[u] = zero2();
-    constexpr int B = 4;   // basis loads in flight per thread
-    for (int j = 0; j < p; j += B) {
-      TQ raw[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) raw[b] = Q[(int64_t)min(j + b, p - 1) * ldq + r];
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        if (j + b >= p) break;
-        const double2 q = cvt(raw[b]);
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (o0 + u < nout) acc[u] = cadd(acc[u], cmul(q, C[(size_t)(o0 + u) * ldc + j + b]));
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (o0 + u < nout) {
-        double2* px = X + (int64_t)(o0 + u) * n + r;
-        *px = cadd(*px, acc[u]);
-      }
+  const int o0 = blockIdx.y * kMgOut;
+  // this block's coefficients in LDS (every thread reads the same entry)
+  extern __shared__ double2 cl[];   // kMgOut x p
+  for (int e = threadIdx.x; e < kMgOut * p; e += NT) {
+    const int u = e / p, jj = e % p;
+    cl[e] = (o0 + u < nout) ? C[(size_t)(o0 + u) * ldc + jj] : zero2();
   }
+  __syncthreads();
+  if (r >= n) return;
+  double2 acc[kMgOut];
+#pragma unroll
+  for (int u = 0; u < kMgOut; ++u) acc[u] = zero2();
+  constexpr int B = 8;   // basis loads in flight per thread
+  for (int j = 0; j < p; j += B) {
+    TQ raw[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) raw[b] = Q[(int64_t)min(j + b, p - 1) * ldq + r];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      if (j + b >= p) break;
+      const double2 q = cvt(raw[b]);
+#pragma unroll
+      for (int u = 0; u < kMgOut; ++u) acc[u] = cadd(acc[u], cmul(q, cl[u * p + j + b]));
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kMgOut; ++u)
+    if (o0 + u < nout) {
+      double2* px = X + (int64_t)(o0 + u) * n + r;
+      *px = cadd(*px, acc[u]);
+    }
 }
 
 template <typename TI, typename TO>
@@ -455,8 +465,8 @@ hipError_t ts_gemv(const TQ* Q, int64_t ldq, int p, const double2* coef, double2
 template <typename TQ>
 hipError_t ts_multi_gemv(const TQ* Q, int64_t ldq, int p, const double2* C, int ldc, int nout,
                          double2* X, int64_t n, const int* pdev, hipStream_t s) {
-  hipLaunchKernelGGL((k_ts_multi_gemv<TQ>), dim3(ts_blocks(n)), dim3(NT), 0, s, Q, ldq, p, C,
-                     ldc, nout, X, n, pdev);
+  hipLaunchKernelGGL((k_ts_multi_gemv<TQ>), dim3(ts_blocks(n), (nout + kMgOut - 1) / kMgOut), dim3(NT),
+                     (size_t)kMgOut * (p > 0 ? p : 1) * sizeof(double2), s, Q, ldq, p, C, ldc, nout, X, n, pdev);
   return hipGetLastError();
 }
 

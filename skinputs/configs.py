@@ -57,7 +57,7 @@ CONFIGS = {
                  scales={0.1: 1.864, 0.3: 1.827}),
     # 10^4, 16 poles, k = 60, 40 deflated, complex-float stencil/basis + FP64
     "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-10,
-                 precision="mixed", scales={0.3: 2.422}),
+                 precision="mixed", scales={0.1: 2.435, 0.3: 2.422}),
     # c3 with the Kenney-Laub order raised to s = 32 (64 poles): the scalar
     # error bound 2 rho^{2s} of g_s on the scaled segment [a, lambda_max]
     # falls from ~1e-2 (s = 8) to ~4e-9, so the result approximates

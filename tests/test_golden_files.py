@@ -2,8 +2,10 @@
 from the CPU oracle only) are internally consistent and match the configs:
 the per-shift residuals of the oracle's unrestarted multishift FOM are at
 rounding level, the deflated eigenpairs are accurate and biorthonormal,
-and the pole scale is the two-circle rule c = (a b)^{-1/2} (Sect. 6) to
-the four digits the configs record."""
+the pole scale is the two-circle rule c = (a b)^{-1/2} (Sect. 6) to the
+four digits the configs record, the stored full x* agrees with the
+stored sample, and where the pole order was doubled the change of x*
+is consistent with the Kenney-Laub error bound of the order."""
 import glob
 import json
 import os
@@ -18,7 +20,7 @@ FILES = sorted(glob.glob(os.path.join(HERE, "*.json")))
 
 def test_there_are_stored_values_for_every_large_config():
     names = {os.path.basename(f) for f in FILES}
-    for must in ["c6_mu0.3.json", "c2_mu0.3.json", "c3_mu0.3.json", "cg_mu0.3.json"]:
+    for must in ["c6_mu0.3.json", "c2_mu0.3.json", "c3_mu0.3.json", "cg_mu0.3.json", "c2_mu0.1.json"]:
         assert must in names
 
 
@@ -40,3 +42,21 @@ def test_stored_oracle_values(path):
         import numpy as np
         lam = np.abs(np.array(g["eig_re"]) + 1j * np.array(g["eig_im"]))
         assert g["a_next"] > lam.max()
+
+    import numpy as np
+    full = path[:-5] + "_x.npy"
+    if os.path.exists(full):
+        x = np.load(full)
+        assert x.shape == (cfg.n,) and x.dtype == np.complex128
+        idx = np.array(g["sample_index"])
+        assert np.array_equal(x[idx], np.array(g["x_re"]) + 1j * np.array(g["x_im"]))
+        assert abs(np.linalg.norm(x) - g["x_norm"]) <= 1e-12 * g["x_norm"]
+    if "order_check" in g:
+        oc = g["order_check"]
+        assert oc["s2"] == 2 * cfg.s and oc["max_shift_residual_s2"] <= 1e-12
+        # ||x*(s) - x*(2s)|| is the approximation error of order s to within
+        # that of order 2s; it must not exceed the scalar bound by much (the
+        # deflated operator is not normal, so allow a modest factor) and must
+        # be well above the order-2s bound
+        assert oc["rel_diff"] <= 100 * g["kl_bound"]
+        assert oc["rel_diff"] >= 10 * oc["kl_bound_s2"] or oc["rel_diff"] < 1e-12

@@ -644,3 +644,30 @@ def test_gmres_lr_short_cycle_divergence_is_reported():
     with np.errstate(all="ignore"):
         x, info = gmres.restarted_gmres_lr(lambda v: A @ v, b, sig, om, 8, max_cycles=2000)
     assert not info["converged"]
+
+
+def test_rational_approximation_error_against_dense_sign():
+    """How close x* (the fixed point of Algorithm 1) is to sign(A) b itself:
+    with the two-circle scale c = (a b)^{-1/2} from the deflated spectrum,
+    the error falls with the Kenney-Laub order s as the scalar bound
+    2 rho^{2s} does, rho = (sqrt(q) - 1)/(sqrt(q) + 1), q = b / a."""
+    dims = (2, 2, 3, 4)
+    V = si.lattice_volume(dims)
+    A = dirac.hw_dense(si.gauge_links(dims, 0.5, 16), dims, 0.25, 0.3)
+    b = si.gaussian_source(12 * V, 17)
+    R, L, lam, F = deflation.lr_dense(A, 10)
+    ev = np.linalg.eigvals(A)
+    a = np.sort(np.abs(ev))[10]
+    bmax = np.max(np.abs(ev))
+    c = (a * bmax) ** -0.5
+    q = bmax / a
+    rho = (np.sqrt(q) - 1) / (np.sqrt(q) + 1)
+    ex = signfun.sign_schur(A) @ b
+    errs = []
+    for s in (4, 8, 16, 32):
+        sig, om = rational.kl_first_order(s, c)
+        e = rel(xstar.xstar_dense(A, b, sig, om, R, L, F), ex)
+        errs.append(e)
+        assert e <= 10 * 2 * rho ** (2 * s) + 1e-13, (s, e, 2 * rho ** (2 * s))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[-1] < 1e-10
