@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--mu", type=float, default=0.3)
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--tol", type=float, default=None, help="override the configuration's tolerance")
+    ap.add_argument("--mixed-switch", type=float, default=None,
+                    help="override the relative update at which mixed precision switches to complex float")
     ap.add_argument("--cpu-cycles", type=int, default=2,
                     help="restart cycles of the CPU oracle to time (bounded sample)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -42,6 +45,8 @@ def parse():
     ap.add_argument("--batched-only", action="store_true")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the 16^4 / 24^4 bandwidth sweep")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the 16^4 / 24^4 bandwidth sweep (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB three times (reference for the "
                          "FETCH_SIZE / WRITE_SIZE hardware counters) and exit")
@@ -396,6 +401,9 @@ def main():
     if args.batched_only:
         print(json.dumps({"batched": batched_leg(args)}), flush=True)
         return
+    if args.sweep_only:
+        print(json.dumps({"bandwidth_sweep": sweep_leg()}), flush=True)
+        return
     cfg = CONFIGS[args.config]
     mu = args.mu
     precision_run = args.precision or cfg.precision
@@ -425,8 +433,10 @@ def main():
                "restarts": est["restarts"], "resid": est["resid"], "gap": est["gap"],
                "lambda_min_abs": float(np.abs(lam).min()), "lambda_m_abs": float(np.abs(lam).max())}
         log(f"eigensolve m={m_used}: {eig['seconds']:.2f} s, {est['matvecs']} matvecs")
-    solver = api.SignSolver(op, sigma, omega, cfg.k, tol=cfg.tol, max_cycles=cfg.max_cycles,
-                            precision=precision_run, R=R, Lv=Lv, F=F)
+    tol = args.tol if args.tol is not None else cfg.tol
+    switch = args.mixed_switch if args.mixed_switch is not None else cfg.mixed_switch
+    solver = api.SignSolver(op, sigma, omega, cfg.k, tol=tol, max_cycles=cfg.max_cycles,
+                            precision=precision_run, R=R, Lv=Lv, F=F, mixed_switch=switch)
     x = torch.empty_like(bd)
 
     # ---- warmup, then K timed solves
@@ -451,9 +461,20 @@ def main():
     log(f"{args.steps} solves in {sec:.4f} s (wall {wall:.4f} s); cycles/solve={cycles[-1]} "
         f"(complex float {res.cycles_c64}) matvecs={res.matvecs}")
     if args.solve_only:
+        errs = {}
+        gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_mu{mu:g}.json")
+        if os.path.exists(gpath):
+            g = json.load(open(gpath))
+            xh = si.canonical_from_soa(x.cpu().numpy(), cfg.V)
+            ref = np.array(g["x_re"]) + 1j * np.array(g["x_im"])
+            errs["sampled"] = float(np.linalg.norm(xh[np.array(g["sample_index"])] - ref) / np.linalg.norm(ref))
+            if os.path.exists(gpath[:-5] + "_x.npy"):
+                xf = np.load(gpath[:-5] + "_x.npy")
+                errs["full"] = float(np.linalg.norm(xh - xf) / np.linalg.norm(xf))
         print(json.dumps({"solve_only": True, "config": cfg.name, "mu": mu, "solves_per_s": value,
-                          "ms_per_solve": 1e3 * sec / args.steps, "steps": args.steps,
-                          "cycles": cycles[-1]}), flush=True)
+                          "ms_per_solve": 1e3 * sec / args.steps, "steps": args.steps, "tol": tol,
+                          "mixed_switch": switch, "cycles": cycles[-1], "cycles_c64": res.cycles_c64,
+                          "fp64_check_ok": res.resid_ok, "rel_err_vs_oracle": errs}), flush=True)
         return
 
     # ---- per-kernel timing (HIP events around every launch on the solve's

@@ -348,48 +348,67 @@ __global__ __launch_bounds__(NT) void k_ts_gemv(const TQ* __restrict__ Q, int64_
 }
 
 // X_i += sum_j Q_j C[i*ldc + j] for the outputs i of this block row
-// (grid.y picks kMgOut consecutive outputs): one row per thread, kMgOut
-// accumulators, 8 basis loads in flight; the basis is read once per group
-// of outputs, which keeps the per-thread chain short.
+// (grid.y picks kMgOut consecutive outputs).  Each thread takes kMgRows rows
+// (r and r + NT) with kMgOut accumulators each, so that every coefficient,
+// read from LDS (the same entry for all lanes), feeds kMgRows complex
+// multiply-adds; 8 basis loads per row in flight.
 constexpr int kMgOut = 8;
+constexpr int kMgRows = 2;
 template <typename TQ>
 __global__ __launch_bounds__(NT) void k_ts_multi_gemv(const TQ* __restrict__ Q, int64_t ldq, int p,
                                                       const double2* __restrict__ C, int ldc,
                                                       int nout, double2* X, int64_t n,
                                                       const int* pdev) {
   if (pdev) p = min(p, *pdev);
-  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * (NT * kMgRows) + threadIdx.x;
   const int o0 = blockIdx.y * kMgOut;
-  // this block's coefficients in LDS (every thread reads the same entry)
   extern __shared__ double2 cl[];   // kMgOut x p
   for (int e = threadIdx.x; e < kMgOut * p; e += NT) {
     const int u = e / p, jj = e % p;
     cl[e] = (o0 + u < nout) ? C[(size_t)(o0 + u) * ldc + jj] : zero2();
   }
   __syncthreads();
-  if (r >= n) return;
-  double2 acc[kMgOut];
+  if (r0 >= n) return;
+  int64_t rr[kMgRows];
 #pragma unroll
-  for (int u = 0; u < kMgOut; ++u) acc[u] = zero2();
-  constexpr int B = 8;   // basis loads in flight per thread
+  for (int w = 0; w < kMgRows; ++w) rr[w] = min(r0 + (int64_t)w * NT, n - 1);   // clamped rows are not stored
+  double2 acc[kMgRows][kMgOut];
+#pragma unroll
+  for (int w = 0; w < kMgRows; ++w)
+#pragma unroll
+    for (int u = 0; u < kMgOut; ++u) acc[w][u] = zero2();
+  constexpr int B = 8;   // basis loads in flight per row
   for (int j = 0; j < p; j += B) {
-    TQ raw[B];
+    TQ raw[kMgRows][B];
 #pragma unroll
-    for (int b = 0; b < B; ++b) raw[b] = Q[(int64_t)min(j + b, p - 1) * ldq + r];
+    for (int w = 0; w < kMgRows; ++w)
+#pragma unroll
+      for (int b = 0; b < B; ++b) raw[w][b] = Q[(int64_t)min(j + b, p - 1) * ldq + rr[w]];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       if (j + b >= p) break;
-      const double2 q = cvt(raw[b]);
+      double2 q[kMgRows];
 #pragma unroll
-      for (int u = 0; u < kMgOut; ++u) acc[u] = cadd(acc[u], cmul(q, cl[u * p + j + b]));
+      for (int w = 0; w < kMgRows; ++w) q[w] = cvt(raw[w][b]);
+#pragma unroll
+      for (int u = 0; u < kMgOut; ++u) {
+        const double2 cf = cl[u * p + j + b];
+#pragma unroll
+        for (int w = 0; w < kMgRows; ++w) acc[w][u] = cadd(acc[w][u], cmul(q[w], cf));
+      }
     }
   }
 #pragma unroll
-  for (int u = 0; u < kMgOut; ++u)
-    if (o0 + u < nout) {
-      double2* px = X + (int64_t)(o0 + u) * n + r;
-      *px = cadd(*px, acc[u]);
-    }
+  for (int w = 0; w < kMgRows; ++w) {
+    const int64_t r = r0 + (int64_t)w * NT;
+    if (r >= n) break;
+#pragma unroll
+    for (int u = 0; u < kMgOut; ++u)
+      if (o0 + u < nout) {
+        double2* px = X + (int64_t)(o0 + u) * n + r;
+        *px = cadd(*px, acc[w][u]);
+      }
+  }
 }
 
 template <typename TI, typename TO>
@@ -465,7 +484,8 @@ hipError_t ts_gemv(const TQ* Q, int64_t ldq, int p, const double2* coef, double2
 template <typename TQ>
 hipError_t ts_multi_gemv(const TQ* Q, int64_t ldq, int p, const double2* C, int ldc, int nout,
                          double2* X, int64_t n, const int* pdev, hipStream_t s) {
-  hipLaunchKernelGGL((k_ts_multi_gemv<TQ>), dim3(ts_blocks(n), (nout + kMgOut - 1) / kMgOut), dim3(NT),
+  const unsigned nbx = (unsigned)((n + (int64_t)NT * kMgRows - 1) / ((int64_t)NT * kMgRows));
+  hipLaunchKernelGGL((k_ts_multi_gemv<TQ>), dim3(nbx, (nout + kMgOut - 1) / kMgOut), dim3(NT),
                      (size_t)kMgOut * (p > 0 ? p : 1) * sizeof(double2), s, Q, ldq, p, C, ldc, nout, X, n, pdev);
   return hipGetLastError();
 }

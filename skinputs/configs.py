@@ -25,6 +25,7 @@ class Config:
     m: int                     # deflation dimension
     tol: float                 # stopping tolerance on the update norm
     precision: str = "fp64"    # "fp64" or "mixed"
+    mixed_switch: float = 0.0  # mixed: relative update at which complex float takes over (0: 1e-3)
     kappa: float = 0.25        # m_W = -2
     antiperiodic_t: bool = True
     max_cycles: int = 400
@@ -55,15 +56,19 @@ CONFIGS = {
     # 8^4, 16 poles, k = 50, 20 deflated (oblique, left + right), complex double
     "c2": Config("c2", (8, 8, 8, 8), 0.6, (0.1, 0.3), s=8, k=50, m=20, tol=1e-10,
                  scales={0.1: 1.864, 0.3: 1.827}),
-    # 10^4, 16 poles, k = 60, 40 deflated, complex-float stencil/basis + FP64
-    "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-10,
-                 precision="mixed", scales={0.1: 2.435, 0.3: 2.422}),
+    # 10^4, 16 poles, k = 60, 40 deflated, complex-float stencil/basis + FP64;
+    # the stopping tolerance sits one decade above the others: the update
+    # norm bounds the remaining error, measured 1.5e-10 against the oracle's
+    # x* at 1e-9 (the target is 1e-8), and complex float takes over at a
+    # relative update of 1e-2 (the FP64 residual check confirms the result)
+    "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-9,
+                 precision="mixed", mixed_switch=1e-2, scales={0.1: 2.435, 0.3: 2.422}),
     # c3 with the Kenney-Laub order raised to s = 32 (64 poles): the scalar
     # error bound 2 rho^{2s} of g_s on the scaled segment [a, lambda_max]
     # falls from ~1e-2 (s = 8) to ~4e-9, so the result approximates
     # sign(H_W) b itself, not only the 16-pole g_8
-    "c3s": Config("c3s", (10, 10, 10, 10), 0.7, (0.3,), s=32, k=60, m=40, tol=1e-10,
-                  precision="mixed", scales={0.3: 2.422}),
+    "c3s": Config("c3s", (10, 10, 10, 10), 0.7, (0.3,), s=32, k=60, m=40, tol=1e-9,
+                  precision="mixed", mixed_switch=1e-2, scales={0.3: 2.422}),
     # 6^4, the smallest lattice of the multi-source batch: 16 poles, k = 40,
     # 10 deflated, complex double reference
     "c6": Config("c6", (6, 6, 6, 6), 0.5, (0.3,), s=8, k=40, m=10, tol=1e-10,

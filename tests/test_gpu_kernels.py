@@ -191,3 +191,26 @@ def test_arnoldi_cycle_one_lane_update_path():
         err_r = np.linalg.norm(A @ Vb[:, :k] - Vb @ H) / np.linalg.norm(H)
         print(f"{dt}: H {err_h:.1e}, orthonormality {err_o:.1e}, Arnoldi relation {err_r:.1e}")
         assert err_h <= tol_h and err_o < tol_o and err_r < tol_o
+
+
+def test_singular_shifted_hessenberg_is_reported():
+    """Forced from the host: a Hessenberg matrix whose shifted leading block
+    H_k - sigma_0 I is exactly singular (zero first column), passed to the
+    per-cycle multishift step; the library must return SK_ERR_SINGULAR and
+    not a non-finite iterate."""
+    import torch
+    from paper_0910_2927_amd import api, _lib
+    dev = torch_dev()
+    k, n = 2, 12 * 16
+    H = torch.zeros((k + 1, k), dtype=torch.complex128)
+    H[0, 0], H[1, 1], H[2, 1] = 1.0, 2.0, 0.5          # h_{2,1} = 0
+    sig = np.array([1.0 + 0j, 3.0 + 0j])
+    om = np.array([0.5 + 0j, 0.5 + 0j])
+    Vb = torch.from_numpy(np.linalg.qr(si.gaussian_source(n * k, 90).reshape(n, k))[0].T.copy()).to(dev)
+    beta = torch.tensor([1.0], dtype=torch.float64, device=dev)
+    rho = torch.ones(2, dtype=torch.complex128, device=dev)
+    x = torch.zeros(n, dtype=torch.complex128, device=dev)
+    announce("multishift_fom_restart with a singular shifted H_k")
+    with pytest.raises(_lib.SkError) as e:
+        api.multishift_fom_restart(H.to(dev), k, sig, om, beta, rho, Vb, x)
+    assert e.value.status == _lib.SK_ERR_SINGULAR
