@@ -68,7 +68,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCES = ("dcgs2_dev.h", "dcgs2.hip", "sk_common.h", "sk_internal.h", "stencil_dev.h", "wilson.hip")
+# sources that define each kernel whose hardware counters are committed
+_GS_SOURCES = ("dcgs2_dev.h", "dcgs2.hip", "sk_common.h", "sk_internal.h")
+KERNEL_SOURCES = {"k_dc_update": _GS_SOURCES, "k_dc_dot": _GS_SOURCES,
+                  "k_wilson": ("stencil_dev.h", "wilson.hip", "sk_common.h", "sk_internal.h")}
 
 # kernel class of the per-kernel timing -> kernel name in a trace
 KERNEL_NAMES = {"stencil": "k_wilson", "gs_dot": "k_dc_dot", "gs_upd_dot": "k_dc_update",
@@ -76,11 +79,11 @@ KERNEL_NAMES = {"stencil": "k_wilson", "gs_dot": "k_dc_dot", "gs_upd_dot": "k_dc
                 "project": "k_cp_apply", "gs_reduce": "k_dc_reduce"}
 
 
-def kernel_source_hash():
-    """sha256 of the sources that define the Gram-Schmidt and stencil kernels."""
+def kernel_source_hash(kernel):
+    """sha256 of the sources that define `kernel`."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES.get(kernel, ()):
         h.update(open(os.path.join(ROOT, "paper_0910_2927_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
@@ -495,7 +498,7 @@ def main():
     achieved = kern[dom]["GBs"]
     counters = load_counters(os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[dom]}_c3_10x4_counters.txt"))
     traffic = None
-    if counters and counters.get("source_sha256") == kernel_source_hash():
+    if counters and counters.get("source_sha256") == kernel_source_hash(KERNEL_NAMES[dom]):
         traffic = counters["traffic_bytes_per_launch"] / (kern[dom]["avg_us"] * 1e-6) / 1e9
     log(f"dominant kernel {KERNEL_NAMES[dom]} ({dom}): {achieved:.0f} GB/s algorithmic, "
         f"{kern[dom]['avg_us']:.1f} us per launch, {kern[dom]['ms']:.2f} ms per solve")

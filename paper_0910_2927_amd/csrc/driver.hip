@@ -406,6 +406,7 @@ struct SignWs {
   double2* rhs;       // (I - P) b
   double2* tmp;       // one shifted residual
   double* resid2;     // npoles squared residual norms, then ||rhs||^2
+  double* rpart;      // per-pole partial sums of the squared residual norms
   double2* rnext;     // GMRES-LR: the next restart vector V_{k+1} z
   double2* zdev;      // GMRES-LR: z (k+1 entries)
 };
@@ -420,6 +421,7 @@ size_t carve_sign(Carver& c, SignWs& sw, int64_t n, const sk_sign_params* p) {
   sw.rhs = keep ? c.take<double2>(n) : nullptr;
   sw.tmp = keep ? c.take<double2>(n) : nullptr;
   sw.resid2 = keep ? c.take<double>(p->npoles + 2) : nullptr;
+  sw.rpart = keep ? c.take<double>((size_t)p->npoles * wilson_residual_partials(n / 12)) : nullptr;
   sw.rnext = p->method == SK_METHOD_GMRES ? c.take<double2>(n) : nullptr;
   sw.zdev = p->method == SK_METHOD_GMRES ? c.take<double2>((size_t)p->k + 1) : nullptr;
   return c.off;
@@ -441,14 +443,12 @@ int true_residuals(const sk_operator* op, const sk_sign_params* p, const PoleSet
   SK_LAUNCH((ts_update<double2, double2, double2>(p->m > 0 ? (const double2*)p->R : nullptr, n, p->m,
                                                   w.dc, nullptr, b, sw.rhs, n, 2, er, w.partial,
                                                   w.counter + 5 * cs, nullptr, s)));
-  for (int i = 0; i < N; ++i) {
+  // the residual stencil leaves per-wave partial norms; one fold per pole
+  const int P = wilson_residual_partials(n / 12);
+  for (int i = 0; i < N; ++i)
     SK_LAUNCH((launch_wilson_residual<double2>(op, (const double2*)op->links, X + (size_t)i * n,
-                                               sw.rhs, ps.sigma[i], sw.tmp, s)));
-    TsEpiArgs en = epi_of(EPI_XNORM, a);
-    en.dst_scalar = sw.resid2 + i;
-    SK_LAUNCH((ts_dot<double2, double2>(nullptr, n, 0, sw.tmp, n, true, en, w.partial,
-                                        w.counter + 4 * cs, nullptr, s)));
-  }
+                                               sw.rhs, ps.sigma[i], sw.tmp, sw.rpart + (size_t)i * P, s)));
+  SK_LAUNCH(launch_fold_rows(sw.rpart, P, N, P, P, sw.resid2, s));
   std::vector<double> r2(N + 1);
   SK_HIP(hipMemcpyAsync(r2.data(), sw.resid2, (N + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
   SK_HIP(hipStreamSynchronize(s));

@@ -128,9 +128,16 @@ hipError_t launch_wilson(const sk_operator* op, const TL* links, const TI* in, T
                          hipStream_t s, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 
 // Residual form: out = b - (H_W - sigma) in, in double; `in` of type TI.
+// rpart (nullable): wilson_residual_partials(V) partial sums of ||out||^2.
 template <typename TI>
 hipError_t launch_wilson_residual(const sk_operator* op, const double2* links, const TI* in,
-                                  const double2* b, double2 sigma, double2* out, hipStream_t s);
+                                  const double2* b, double2 sigma, double2* out, double* rpart,
+                                  hipStream_t s);
+int wilson_residual_partials(int64_t V);
+// rows[i] = sum of part[i * stride + 0 .. cnt_i), cnt_i = cnt for i < nrows - 1 and
+// cnt_last for the last row; one block per row, fixed order.
+hipError_t launch_fold_rows(const double* part, int64_t stride, int nrows, int cnt, int cnt_last,
+                            double* rows, hipStream_t s);
 
 // DOT: sums_i = sum_r conj(Q_i[r]) v[r] (i < p), plus ||v||^2 if with_norm.
 template <typename TQ, typename TV>

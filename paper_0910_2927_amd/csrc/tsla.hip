@@ -432,6 +432,23 @@ __global__ __launch_bounds__(NT) void k_scale_basis(T* Q, int64_t ldq, int p, co
   st(q, cscale(ld(q), scale[j]));
 }
 
+__global__ __launch_bounds__(NT) void k_fold_rows(const double* __restrict__ part, int64_t stride, int nrows,
+                                                  int cnt, int cnt_last, double* __restrict__ rows) {
+  __shared__ double red[NW];
+  const int i = blockIdx.x;
+  const int c = (i == nrows - 1) ? cnt_last : cnt;
+  double a = 0.0;
+  for (int e = threadIdx.x; e < c; e += NT) a += part[(size_t)i * stride + e];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    rows[i] = t;
+  }
+}
+
 __global__ void k_init_state(CycleState* st, double2* rho, int npoles, unsigned* counter, int ncnt) {
   const int t = threadIdx.x;
   if (t == 0) {
@@ -513,6 +530,12 @@ template hipError_t ts_scale_basis<float2>(float2*, int64_t, int, const double*,
 hipError_t launch_init_state(CycleState* st, double2* rho, int npoles, unsigned* counter, int ncnt,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3(1), dim3(256), 0, s, st, rho, npoles, counter, ncnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_rows(const double* part, int64_t stride, int nrows, int cnt, int cnt_last,
+                            double* rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold_rows, dim3(nrows), dim3(NT), 0, s, part, stride, nrows, cnt, cnt_last, rows);
   return hipGetLastError();
 }
 

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kStencilThreads) void k_wilson(StencilGeom g, const
                                                             TO* __restrict__ out,
                                                             const double* in_scale, const int* skip,
                                                             const double2* __restrict__ b,
-                                                            double2 sigma) {
+                                                            double2 sigma, double* __restrict__ rpart) {
   if (skip && *skip) return;
   const double sc = (MODE == 0 && in_scale) ? *in_scale : 1.0;
   __shared__ double2 hs[8][6][64];
@@ -95,31 +95,43 @@ __global__ __launch_bounds__(kStencilThreads) void k_wilson(StencilGeom g, const
     }
   }
   __syncthreads();
-  if (h >= 3 || !act) return;
+  if (h >= 3) return;
   const int a = h;   // colour handled by this wave
-  double2 acc[4];
+  double r2 = 0.0;   // MODE 1: this lane's share of ||out||^2
+  if (act) {
+    double2 acc[4];
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp) acc[sp] = make_double2(0.0, 0.0);
-  add_hop<0>(acc, hs[0], a, lane);
-  add_hop<1>(acc, hs[1], a, lane);
-  add_hop<2>(acc, hs[2], a, lane);
-  add_hop<3>(acc, hs[3], a, lane);
-  add_hop<4>(acc, hs[4], a, lane);
-  add_hop<5>(acc, hs[5], a, lane);
-  add_hop<6>(acc, hs[6], a, lane);
-  add_hop<7>(acc, hs[7], a, lane);
+    for (int sp = 0; sp < 4; ++sp) acc[sp] = make_double2(0.0, 0.0);
+    add_hop<0>(acc, hs[0], a, lane);
+    add_hop<1>(acc, hs[1], a, lane);
+    add_hop<2>(acc, hs[2], a, lane);
+    add_hop<3>(acc, hs[3], a, lane);
+    add_hop<4>(acc, hs[4], a, lane);
+    add_hop<5>(acc, hs[5], a, lane);
+    add_hop<6>(acc, hs[6], a, lane);
+    add_hop<7>(acc, hs[7], a, lane);
 #pragma unroll
-  for (int sp = 0; sp < 4; ++sp) {
-    const int c = sp * 3 + a;
-    const double2 xin = cvt(xd[sp]);
-    double2 v = cadd(xin, acc[sp]);                    // D_W psi
-    if (sp >= 2) v = make_double2(-v.x, -v.y);         // gamma5
-    if constexpr (MODE == 0) {
-      st(out + c * g.V + s, cscale(v, sc));
-    } else {
-      v = csub(v, cmul(sigma, xin));
-      st(out + c * g.V + s, csub(b[c * g.V + s], v));
+    for (int sp = 0; sp < 4; ++sp) {
+      const int c = sp * 3 + a;
+      const double2 xin = cvt(xd[sp]);
+      double2 v = cadd(xin, acc[sp]);                    // D_W psi
+      if (sp >= 2) v = make_double2(-v.x, -v.y);         // gamma5
+      if constexpr (MODE == 0) {
+        st(out + c * g.V + s, cscale(v, sc));
+      } else {
+        v = csub(v, cmul(sigma, xin));
+        const double2 r = csub(b[c * g.V + s], v);
+        st(out + c * g.V + s, r);
+        r2 += cabs2(r);
+      }
     }
+  }
+  // MODE 1: each of a block's three colour waves writes one partial sum
+  // (all 64 lanes take part; lanes past the lattice add 0), folded later
+  // in a fixed order
+  if (MODE == 1 && rpart) {
+    const double w = wave_sum(r2);
+    if (lane == 0) rpart[(size_t)blockIdx.x * 3 + a] = w;
   }
 }
 
@@ -137,22 +149,26 @@ hipError_t launch_wilson(const sk_operator* op, const TL* links, const TI* in, T
   if (t0 || t1)
     hipExtLaunchKernelGGL((k_wilson<0, TI, TL, TO>), dim3(stencil_blocks(g.V)), dim3(kStencilThreads), 0,
                           s, t0, t1, 0, g, links, in, out, in_scale, skip, (const double2*)nullptr,
-                          make_double2(0.0, 0.0));
+                          make_double2(0.0, 0.0), (double*)nullptr);
   else
     hipLaunchKernelGGL((k_wilson<0, TI, TL, TO>), dim3(stencil_blocks(g.V)), dim3(kStencilThreads), 0, s,
-                       g, links, in, out, in_scale, skip, (const double2*)nullptr, make_double2(0.0, 0.0));
+                       g, links, in, out, in_scale, skip, (const double2*)nullptr, make_double2(0.0, 0.0),
+                       (double*)nullptr);
   return hipGetLastError();
 }
 
 template <typename TI>
 hipError_t launch_wilson_residual(const sk_operator* op, const double2* links, const TI* in,
-                                  const double2* b, double2 sigma, double2* out, hipStream_t s) {
+                                  const double2* b, double2 sigma, double2* out, double* rpart,
+                                  hipStream_t s) {
   StencilGeom g = make_geom(op, 0);
   hipLaunchKernelGGL((k_wilson<1, TI, double2, double2>), dim3(stencil_blocks(g.V)),
                      dim3(kStencilThreads), 0, s, g, links, in, out, (const double*)nullptr,
-                     (const int*)nullptr, b, sigma);
+                     (const int*)nullptr, b, sigma, rpart);
   return hipGetLastError();
 }
+
+int wilson_residual_partials(int64_t V) { return 3 * stencil_blocks((int)V); }
 
 template hipError_t launch_wilson<double2, double2, double2>(const sk_operator*, const double2*,
                                                              const double2*, double2*, int,
@@ -164,9 +180,9 @@ template hipError_t launch_wilson<float2, float2, float2>(const sk_operator*, co
                                                           hipEvent_t, hipEvent_t);
 template hipError_t launch_wilson_residual<double2>(const sk_operator*, const double2*,
                                                     const double2*, const double2*, double2,
-                                                    double2*, hipStream_t);
+                                                    double2*, double*, hipStream_t);
 template hipError_t launch_wilson_residual<float2>(const sk_operator*, const double2*,
                                                    const float2*, const double2*, double2,
-                                                   double2*, hipStream_t);
+                                                   double2*, double*, hipStream_t);
 
 }  // namespace sk
