@@ -454,9 +454,8 @@ __global__ void k_binit(const BSys* __restrict__ sys, int nsys, int npoles) {
   for (int i = threadIdx.x; i < 2 * (k + 2); i += blockDim.x) S.sbuf[i] = make_double2(0.0, 0.0);
   if (threadIdx.x == 0) {
     CycleState* st = S.arn.st;
-    st->beta = st->xnorm2 = st->upd_norm = st->leak = st->hnext = st->first_upd = 0.0;
+    st->beta = st->xnorm2 = st->upd_norm = st->leak = st->hnext = 0.0;
     st->kdone = st->breakdown = st->singular = st->nonfinite = 0;
-    st->halt = st->stop = st->small = st->ncyc = 0;
   }
 }
 

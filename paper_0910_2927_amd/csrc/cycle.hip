@@ -18,8 +18,7 @@ template <typename T>
 __global__ __launch_bounds__(kCT) void k_cx_update(const T* __restrict__ W, int64_t n,
                                                    const double2* __restrict__ ucoef,
                                                    const int* __restrict__ kdone, double2* __restrict__ x,
-                                                   double* __restrict__ xpart, const int* stop) {
-  if (*stop) return;
+                                                   double* __restrict__ xpart) {
   __shared__ double2 c[kMaxK + 2];
   __shared__ double red[kCW];
   const int kk = *kdone;
@@ -53,7 +52,6 @@ __global__ __launch_bounds__(kCT) void k_cx_update(const T* __restrict__ W, int6
 
 __global__ __launch_bounds__(kCT) void k_cx_norm(const double* __restrict__ xpart, int nb,
                                                  CycleState* st) {
-  if (st->stop) return;
   __shared__ double red[kCW];
   double a = 0.0;
   for (int b = threadIdx.x; b < nb; b += kCT) a += xpart[b];
@@ -144,41 +142,7 @@ __global__ __launch_bounds__(kCT) void k_cp_apply(const double2* __restrict__ R,
   st(out + r, w);
 }
 
-// Termination test of restarted FOM after a cycle, in the order the host
-// used to apply it: a non-finite value, a singular shifted system or a
-// breakdown end the solve; otherwise the update u must have met
-// ||u|| <= tol ||x|| in two consecutive cycles, and an update 1e10 times
-// the first cycle's counts as divergence.  Once stop is set, every kernel
-// of a cycle enqueued later returns at once.
-__global__ void k_cycle_gate(CycleState* st, double tol) {
-  if (threadIdx.x != 0 || st->stop) return;
-  int code = 0;
-  if (st->nonfinite) {
-    code = kStopNonfinite;
-  } else if (st->singular) {
-    code = kStopSingular;
-  } else if (st->breakdown) {
-    code = kStopBreakdown;
-  } else {
-    const double u = st->upd_norm;
-    st->small = (u <= tol * sqrt(st->xnorm2)) ? st->small + 1 : 0;
-    if (st->small >= 2) code = kStopConverged;
-    else if (st->ncyc == 0) st->first_upd = u;
-    else if (u > kDivergeFactor * st->first_upd) code = kStopDiverged;
-  }
-  st->ncyc += 1;
-  if (code) {
-    st->stop = code;
-    st->halt = 1;
-  }
-}
-
 }  // namespace
-
-hipError_t cycle_gate(CycleState* st, double tol, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_gate, dim3(1), dim3(64), 0, s, st, tol);
-  return hipGetLastError();
-}
 
 int cycle_xpart_entries(int64_t n) { return (int)((n + kCT - 1) / kCT); }
 int cycle_dpart_rows(int64_t n) { return (int)((n + (int64_t)kCT * kDefRpt - 1) / ((int64_t)kCT * kDefRpt)); }
@@ -187,8 +151,7 @@ template <typename T>
 hipError_t cycle_x_update(const T* W, int64_t n, const double2* ucoef, const int* kdone, double2* x,
                           double* xpart, CycleState* st, hipStream_t s) {
   const int nb = cycle_xpart_entries(n);
-  hipLaunchKernelGGL((k_cx_update<T>), dim3(nb), dim3(kCT), 0, s, W, n, ucoef, kdone, x, xpart,
-                     (const int*)&st->stop);
+  hipLaunchKernelGGL((k_cx_update<T>), dim3(nb), dim3(kCT), 0, s, W, n, ucoef, kdone, x, xpart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cx_norm, dim3(1), dim3(kCT), 0, s, xpart, nb, st);

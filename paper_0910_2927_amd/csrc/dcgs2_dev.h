@@ -335,7 +335,6 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
       if (bad) arn.st->nonfinite = 1;
       if (brk) {
         arn.st->breakdown = 1;
-        arn.st->halt = 1;
         arn.st->kdone = j;
         if (j > 0 && !fresh) arn.H[(size_t)(j - 1) * arn.ldh + j] = z2();
       } else {

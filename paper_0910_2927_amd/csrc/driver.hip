@@ -7,7 +7,6 @@
 #include <chrono>
 #include <cstring>
 #include <list>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -200,8 +199,6 @@ __global__ void k_prep_small(double* scale, int k, CycleState* st, const double*
     st->breakdown = 0;
     st->singular = 0;
     st->nonfinite = 0;
-    st->halt = 0;
-    st->stop = 0;
   }
 }
 
@@ -485,7 +482,7 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   const int64_t n = ca.n;
   const int k = ca.p->k, m = ca.p->m, N = ca.ps->n;
   const ArnoldiDev a = arn_of(w, k);
-  const int* skip = &w.st->halt;
+  const int* skip = &w.st->breakdown;
   KTimer& tm = *ca.tm;
   const double cb = (double)sizeof(T), nn = (double)n;
   const double2* R = (const double2*)ca.p->R;
@@ -499,7 +496,7 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
   tm.end();
   if (ca.X) {
     tm.begin(SK_K_SOL_UPDATE, k * nn * cb + 2.0 * N * nn * 16.0);
-    SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, ca.X, n, &w.st->kdone, ca.s, &w.st->stop)));
+    SK_LAUNCH((ts_multi_gemv<T>(w.W, n, k, w.ycoef, k, N, ca.X, n, &w.st->kdone, ca.s)));
     tm.end();
   }
   // r = v_{k+1};  r = (I - P) r  (projection step); ||r|| is taken by the
@@ -510,7 +507,6 @@ int enqueue_cycle(const CycleArgs& ca, SignWs& sw) {
                              nn * (double)sizeof(TN));
   SK_LAUNCH((cycle_restart<T, TN>(R, Lv, m, proj, Wk, wn.W, n, w.partial, w.st, skip, ca.s)));
   tm.end();
-  SK_LAUNCH(cycle_gate(w.st, ca.p->tol, ca.s));
   return SK_OK;
 }
 
@@ -575,7 +571,6 @@ std::string graph_key(const sk_operator* op, const sk_sign_params* p, const void
   put_bytes(k, p->L);
   put_bytes(k, p->F);
   put_bytes(k, p->project_each_cycle);
-  put_bytes(k, p->tol);
   put_bytes(k, p->precision);
   put_bytes(k, p->X_shift);
   put_bytes(k, x);
@@ -632,41 +627,6 @@ int run_cycle(int kind, const CycleArgs& ca, SignWs& sw, CycleGraphs& g, bool us
   }
   SK_HIP(hipGraphLaunch(g.exec[kind], ca.s));
   return SK_OK;
-}
-
-// Pinned host copies of the cycle state and of rho (two of each,
-// alternating) and the events that mark them written, per thread and
-// device; kept until the process ends (no teardown after the HIP runtime
-// may be gone).
-struct HostSlots {
-  CycleState* st = nullptr;
-  double2* rho = nullptr;   // 2 x kMaxPoles
-  hipEvent_t ev[2] = {nullptr, nullptr};
-};
-
-HostSlots& host_slots() {
-  thread_local std::map<int, HostSlots> per_dev;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
-  HostSlots& h = per_dev[dev];
-  if (!h.st && dev >= 0) {
-    void* mem = nullptr;
-    static_assert(sizeof(CycleState) % 16 == 0, "rho slots follow the states");
-    if (hipHostMalloc(&mem, 2 * sizeof(CycleState) + 2 * kMaxPoles * sizeof(double2), hipHostMallocDefault) !=
-        hipSuccess)
-      return h;
-    if (hipEventCreateWithFlags(&h.ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h.ev[1], hipEventDisableTiming) != hipSuccess) {
-      for (auto& e : h.ev)
-        if (e) hipEventDestroy(e);
-      h.ev[0] = h.ev[1] = nullptr;
-      hipHostFree(mem);
-      return h;
-    }
-    h.st = (CycleState*)mem;
-    h.rho = (double2*)(h.st + 2);
-  }
-  return h;
 }
 
 int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, double2* x,
@@ -750,55 +710,26 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
   std::shared_ptr<CycleGraphs> gptr = use_graph ? graphs_for(graph_key(op, p, x, X, ws))
                                                 : std::make_shared<CycleGraphs>();
   CycleGraphs& graphs = *gptr;
-  int status = SK_ERR_NOCONV;
+  int small = 0, status = SK_ERR_NOCONV;
+  double first_upd = 0.0;
   bool diverged = false;
   std::vector<double2> rho_h(N);
   const bool want_rho = stats && stats->hist_rho;
-  // The termination test runs on the device at the end of every cycle, so
-  // the next cycle can be enqueued before this one's state is read back
-  // (one cycle of lookahead): the GPU goes from cycle to cycle without
-  // waiting for the host.  A cycle enqueued after the solve has ended
-  // returns from every kernel at once.  Per-kernel timing reads its events
-  // cycle by cycle, so it runs without lookahead.
-  const int ahead = use_graph ? 1 : 0;
-  HostSlots& hsl = host_slots();
-  if (!hsl.st) {
-    set_error("pinned host memory for the cycle state is not available");
-    return SK_ERR_HIP;
-  }
-  bool low_c = low;          // precision of the cycle enqueued next
-  std::vector<char> low_of;  // precision of every enqueued cycle
-  std::vector<char> met;     // per cycle read: its update met the switch test
-  int enq = 0, seen = -1;    // cycles enqueued; last cycle whose state was read
-  auto enqueue_next = [&]() -> int {
-    // precision of the cycle after the one enqueued now (cycle enq + 1):
-    // from the state of cycle enq - 2, the newest one read by then with
-    // lookahead; the same lag without it, so that both give the same
-    // iterate bit for bit
-    const bool low_n = low_c || (sw.mixed && enq >= 2 && met[enq - 2]);
-    SK_TRY(run_cycle(!low_c ? (low_n ? 1 : 0) : 2, ca, sw, graphs, use_graph));
-    SK_HIP(hipMemcpyAsync(&hsl.st[enq & 1], w.st, sizeof(CycleState), hipMemcpyDeviceToHost, s));
-    if (want_rho && enq < stats->hist_cap)
-      SK_HIP(hipMemcpyAsync(hsl.rho + (size_t)(enq & 1) * kMaxPoles, w.rho, N * sizeof(double2),
-                            hipMemcpyDeviceToHost, s));
-    SK_HIP(hipEventRecord(hsl.ev[enq & 1], s));
-    low_of.push_back(low_c ? 1 : 0);
-    low_c = low_n;
-    ++enq;
-    return SK_OK;
-  };
-  if (p->max_cycles > 0) SK_TRY(enqueue_next());
   for (int cyc = 0; cyc < p->max_cycles; ++cyc) {
-    if (ahead && enq < p->max_cycles) SK_TRY(enqueue_next());
-    SK_HIP(hipEventSynchronize(hsl.ev[cyc & 1]));
-    hs = hsl.st[cyc & 1];
-    seen = cyc;
-    met.push_back(hs.upd_norm <= theta * std::sqrt(hs.xnorm2) ? 1 : 0);
-    const bool cur = low_of[cyc] != 0;
+    // the next cycle's precision is decided before this one is enqueued:
+    // once low, it stays low
+    const bool low_next = low || (sw.mixed && cyc > 0 && hs.upd_norm <= theta * std::sqrt(hs.xnorm2));
+    const bool cur = low;
+    SK_TRY(run_cycle(!cur ? (low_next ? 1 : 0) : 2, ca, sw, graphs, use_graph));
+    low = low_next;
+    SK_HIP(hipMemcpyAsync(&hs, w.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    if (want_rho && cyc < stats->hist_cap)
+      SK_HIP(hipMemcpyAsync(rho_h.data(), w.rho, N * sizeof(double2), hipMemcpyDeviceToHost, s));
+    SK_HIP(hipStreamSynchronize(s));
     tm.flush();
     if (want_rho && cyc < stats->hist_cap)
       for (int i = 0; i < N; ++i)
-        stats->hist_rho[(size_t)cyc * N + i] = std::sqrt(cabs2(hsl.rho[(size_t)(cyc & 1) * kMaxPoles + i]));
+        stats->hist_rho[(size_t)cyc * N + i] = std::sqrt(cabs2(rho_h[i]));
     if (stats) {
       stats->cycles = cyc + 1;
       stats->cycles_c64 += cur ? 1 : 0;
@@ -811,38 +742,36 @@ int sign_impl(const sk_operator* op, const sk_sign_params* p, const double2* b, 
         if (stats->hist_leak) stats->hist_leak[cyc] = hs.leak;
       }
     }
-    if (hs.stop == kStopNonfinite) {
+    if (hs.nonfinite) {
       set_error("non-finite value in cycle %d (restarted FOM diverged or bad input)", cyc + 1);
       status = SK_ERR_NAN;
       break;
     }
-    if (hs.stop == kStopSingular) {
+    if (hs.singular) {
       set_error("H_k - sigma_i singular in cycle %d", cyc + 1);
       status = SK_ERR_SINGULAR;
       break;
     }
-    if (hs.stop == kStopBreakdown) {
+    if (hs.breakdown) {
       if (stats) stats->breakdown = 1;
       status = SK_OK;
       break;
     }
-    if (hs.stop == kStopConverged) {
+    small = (hs.upd_norm <= p->tol * std::sqrt(hs.xnorm2)) ? small + 1 : 0;
+    if (small >= 2) {
       status = SK_OK;
       break;
     }
     // restarted FOM is not monotone; an update 1e10 times the first one
     // means the restarted iteration diverges for this k
-    if (hs.stop == kStopDiverged) {
+    if (cyc == 0) first_upd = hs.upd_norm;
+    else if (hs.upd_norm > kDivergeFactor * first_upd) {
       set_error("restarted FOM diverged (cycle %d, update %.3e): try another restart length",
                 cyc + 1, hs.upd_norm);
       diverged = true;
       break;
     }
-    if (!ahead && enq < p->max_cycles) SK_TRY(enqueue_next());
   }
-  // a cycle enqueued ahead of the end has returned from all its kernels;
-  // wait for it so that its state copy lands before the slots are reused
-  if (enq > seen + 1) SK_HIP(hipEventSynchronize(hsl.ev[(enq - 1) & 1]));
   if (stats) stats->converged = (status == SK_OK);
   if (status == SK_ERR_NOCONV && !diverged) set_error("not converged after %d cycles", p->max_cycles);
   // FP64 check of the per-shift solutions: always in mixed precision (the

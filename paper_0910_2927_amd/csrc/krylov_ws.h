@@ -207,7 +207,7 @@ int enqueue_arnoldi(const sk_operator* op, const KrylovWs<T>& w, int64_t n, int 
                     T* tmp = nullptr) {
   const ArnoldiDev a = arn_of(w, k);
   const T* U = links_as<T>(op);
-  const int* skip = &w.st->halt;
+  const int* skip = &w.st->breakdown;
   // every buffer the step kernels index must be there and large enough
   if (!w.W || !w.H || !w.st || !w.sbuf || !w.gpart || w.sbuf_k < k ||
       w.gpart_cap < gs_part_entries(sd_row_blocks(n), k) || (power == 2 && !tmp)) {

@@ -24,16 +24,8 @@ struct CycleState {
   int breakdown;      // lucky breakdown happened in this cycle
   int singular;       // some H_k - sigma_i had a zero pivot
   int nonfinite;      // a NaN / Inf showed up
-  // termination decided on the device (restarted FOM), so that the host
-  // may enqueue the next cycle before it has read this one's state:
-  int halt;           // skip flag of the Arnoldi and restart kernels (breakdown or stop)
-  int stop;           // kStop* reason; every kernel of a later cycle then returns at once
-  int small;          // consecutive cycles whose update met the tolerance
-  int ncyc;           // cycles the termination test has seen
-  double first_upd;   // update norm of the first cycle (divergence reference)
+  double pad[2];
 };
-constexpr int kStopConverged = 1, kStopDiverged = 2, kStopBreakdown = 3, kStopSingular = 4,
-              kStopNonfinite = 5;
 
 // Device bookkeeping of one Arnoldi cycle.
 struct ArnoldiDev {
@@ -167,12 +159,10 @@ hipError_t ts_gemv(const TQ* Q, int64_t ldq, int p, const double2* coef, double2
                    double2* partial, unsigned* counter, const int* pdev, const int* skip,
                    hipStream_t s);
 
-// Multi-output GEMV for per-shift solutions: X_i += sum_j Q_j C[i*ldc + j]
-// (nothing when skip is non-NULL and *skip != 0).
+// Multi-output GEMV for per-shift solutions: X_i += sum_j Q_j C[i*ldc + j].
 template <typename TQ>
 hipError_t ts_multi_gemv(const TQ* Q, int64_t ldq, int p, const double2* C, int ldc, int nout,
-                         double2* X, int64_t n, const int* pdev, hipStream_t s,
-                         const int* skip = nullptr);
+                         double2* X, int64_t n, const int* pdev, hipStream_t s);
 
 // Q_j *= scale[j] for j < min(p, *pdev + 1).
 template <typename T>
@@ -199,11 +189,9 @@ hipError_t launch_fom_small(const ArnoldiDev& arn, int k, const PoleSet& poles,
                             double2* ycoef, hipStream_t s);
 
 // End of a restart cycle without fences (cycle.hip): x += V_kk u and
-// st->xnorm2 (xpart: cycle_xpart_entries(n) doubles; nothing once
-// st->stop is set), and the restart vector out = (I - R L^H) v (project)
-// or v, with st->leak = ||L^H v|| (dpart: cycle_dpart_rows(n) x m complex).
-// cycle_gate: the termination test of restarted FOM at the end of a cycle
-// (sets st->stop and st->halt).
+// st->xnorm2 (xpart: cycle_xpart_entries(n) doubles), and the restart
+// vector out = (I - R L^H) v (project) or v, with st->leak = ||L^H v||
+// (dpart: cycle_dpart_rows(n) x m complex).
 int cycle_xpart_entries(int64_t n);
 int cycle_dpart_rows(int64_t n);
 template <typename T>
@@ -212,7 +200,6 @@ hipError_t cycle_x_update(const T* W, int64_t n, const double2* ucoef, const int
 template <typename T, typename TN>
 hipError_t cycle_restart(const double2* R, const double2* L, int m, bool project, const T* v, TN* out,
                          int64_t n, double2* dpart, CycleState* st, const int* skip, hipStream_t s);
-hipError_t cycle_gate(CycleState* st, double tol, hipStream_t s);
 
 // Link and mu gradient of Re<eta, g(H) b> from per-shift solutions (backward.hip).
 int grad_blocks(int64_t V);

@@ -16,14 +16,12 @@ constexpr int kPoleWaves = 4;   // poles (waves) per workgroup
 
 __global__ __launch_bounds__(kPoleWaves * 64) void k_fom_poles(ArnoldiDev arn, int kmax, PoleSet poles,
                                                                double2* rho, double2* Y, double2* Ubuf) {
-  if (arn.st->stop) return;   // a cycle enqueued after the solve had ended
   fom_poles_body(arn, kmax, poles, rho, Y, Ubuf);
 }
 
 __global__ __launch_bounds__(kWaves * 64) void k_fom_combine(ArnoldiDev arn, int kmax, PoleSet poles,
                                                              const double2* Y, double2* ucoef,
                                                              double2* ycoef) {
-  if (arn.st->stop) return;
   const int kk = arn.st->kdone;
   if (kk < 1) {   // no Krylov vector (zero start): no update
     if (threadIdx.x == 0) {

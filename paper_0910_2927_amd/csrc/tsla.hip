@@ -96,13 +96,11 @@ __device__ void run_epilogue(const TsEpiArgs& e, const double2* sums, int p) {
         if (!isfinite(nrm) || !isfinite(ref)) {
           a.st->nonfinite = 1;
           a.st->breakdown = 1;
-          a.st->halt = 1;
           a.st->kdone = j + 1;
           a.H[idx] = zero2();
           a.scale[j + 1] = 0.0;
         } else if (nrm <= kBreakdownTol * ref) {
           a.st->breakdown = 1;
-          a.st->halt = 1;
           a.st->kdone = j + 1;
           a.H[idx] = zero2();
           a.scale[j + 1] = 0.0;
@@ -360,8 +358,7 @@ template <typename TQ>
 __global__ __launch_bounds__(NT) void k_ts_multi_gemv(const TQ* __restrict__ Q, int64_t ldq, int p,
                                                       const double2* __restrict__ C, int ldc,
                                                       int nout, double2* X, int64_t n,
-                                                      const int* pdev, const int* skip) {
-  if (skip && *skip) return;
+                                                      const int* pdev) {
   if (pdev) p = min(p, *pdev);
   const int64_t r0 = (int64_t)blockIdx.x * (NT * kMgRows) + threadIdx.x;
   const int o0 = blockIdx.y * kMgOut;
@@ -457,7 +454,6 @@ __global__ void k_init_state(CycleState* st, double2* rho, int npoles, unsigned*
   if (t == 0) {
     st->beta = 0.0; st->xnorm2 = 0.0; st->upd_norm = 0.0; st->leak = 0.0; st->hnext = 0.0;
     st->kdone = 0; st->breakdown = 0; st->singular = 0; st->nonfinite = 0;
-    st->halt = 0; st->stop = 0; st->small = 0; st->ncyc = 0; st->first_upd = 0.0;
   }
   for (int i = t; i < npoles; i += blockDim.x) rho[i] = make_double2(1.0, 0.0);
   for (int i = t; i < ncnt; i += blockDim.x) counter[i] = 0u;
@@ -504,10 +500,10 @@ hipError_t ts_gemv(const TQ* Q, int64_t ldq, int p, const double2* coef, double2
 
 template <typename TQ>
 hipError_t ts_multi_gemv(const TQ* Q, int64_t ldq, int p, const double2* C, int ldc, int nout,
-                         double2* X, int64_t n, const int* pdev, hipStream_t s, const int* skip) {
+                         double2* X, int64_t n, const int* pdev, hipStream_t s) {
   const unsigned nbx = (unsigned)((n + (int64_t)NT * kMgRows - 1) / ((int64_t)NT * kMgRows));
   hipLaunchKernelGGL((k_ts_multi_gemv<TQ>), dim3(nbx, (nout + kMgOut - 1) / kMgOut), dim3(NT),
-                     (size_t)kMgOut * (p > 0 ? p : 1) * sizeof(double2), s, Q, ldq, p, C, ldc, nout, X, n, pdev, skip);
+                     (size_t)kMgOut * (p > 0 ? p : 1) * sizeof(double2), s, Q, ldq, p, C, ldc, nout, X, n, pdev);
   return hipGetLastError();
 }
 
@@ -593,9 +589,9 @@ template hipError_t ts_gemv<float2>(const float2*, int64_t, int, const double2*,
                                     int64_t, bool, int, const TsEpiArgs&, double2*, unsigned*,
                                     const int*, const int*, hipStream_t);
 template hipError_t ts_multi_gemv<double2>(const double2*, int64_t, int, const double2*, int,
-                                           int, double2*, int64_t, const int*, hipStream_t, const int*);
+                                           int, double2*, int64_t, const int*, hipStream_t);
 template hipError_t ts_multi_gemv<float2>(const float2*, int64_t, int, const double2*, int, int,
-                                          double2*, int64_t, const int*, hipStream_t, const int*);
+                                          double2*, int64_t, const int*, hipStream_t);
 template hipError_t ts_scale<double2, double2>(const double2*, double2*, int64_t, const double*,
                                                double, hipStream_t);
 template hipError_t ts_scale<float2, float2>(const float2*, float2*, int64_t, const double*,
