@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--batched-tile", default=None,
                     help="dot,update,rhs: fix the batched launch shapes (skips the tuner; for "
                          "profiler runs of --batched-only)")
+    ap.add_argument("--batched-profile", action="store_true",
+                    help="with --batched-only: stop after the warm-up and the timed batched solve "
+                         "(a kernel trace then holds those two solves' launches only)")
     ap.add_argument("--batched-switch", type=float, default=1e-2,
                     help="relative update below which the batch switches to complex float "
                          "(the single-source solves keep the library's 1e-3)")
@@ -125,6 +128,45 @@ def kernel_times(lib, solver, b, x, stream):
                           "bytes_per_launch": times.bytes[i] / times.launches[i],
                           "GBs": times.bytes[i] / (times.ms[i] * 1e-3) / 1e9 if times.ms[i] > 0 else None}
     return kern, st
+
+
+def launch_floor(nbytes, reps=100):
+    """Floors for a kernel that moves nbytes, on the GPU side of launches
+    (a HIP graph of reps back-to-back kernels, replayed; HIP events around
+    the replay): a one-block elementwise kernel, and a device copy whose
+    read + write traffic is nbytes."""
+    import torch
+    tiny = torch.zeros(1, device="cuda")
+    src = torch.zeros(max(1, int(nbytes) // 8), dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+
+    def per_launch_us(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, 1e3 * e0.elapsed_time(e1) / reps)
+        return best
+
+    return {"launch_floor_us": per_launch_us(lambda: tiny.add_(1.0)),
+            "copy_same_bytes_us": per_launch_us(lambda: dst.copy_(src)), "bytes": int(nbytes),
+            "note": "per kernel in a replayed graph of back-to-back launches"}
 
 
 def sweep_leg():
@@ -319,6 +361,16 @@ def batched_leg(args, log_prefix="batched"):
     tb = time.perf_counter() - t0
     log(f"{log_prefix}: {nsys} systems in one batch: {tb:.3f} s "
         f"(cycles {min(r.cycles for r in res)}..{max(r.cycles for r in res)})")
+    if args.batched_profile:            # the two batched solves only, for a kernel trace
+        return {"systems": nsys, "batched_seconds": tb, "tile": solver.tile}
+    # per launch class: HIP events that the launches stamp (plain launches,
+    # one more solve), algorithmic bytes summed over the systems live in each
+    # cycle
+    xk = [torch.empty_like(b) for b in bs]
+    solver(bs, xk, kernel_times=True)
+    bkern = solver.kernel_times
+    log(f"{log_prefix}: kernel classes: " + ", ".join(
+        f"{k_}: {v['ms']:.1f} ms/{v['launches']} ({v['GBs'] or 0:.0f} GB/s)" for k_, v in bkern.items()))
     # the same solves one by one in complex double
     ts, errs, cyc1 = 0.0, [], []
     z = 0
@@ -375,7 +427,7 @@ def batched_leg(args, log_prefix="batched"):
             "max_rel_diff_vs_fp64": max(errs), "max_rel_diff_vs_fp64_per_lattice": per_lat,
             "sampled_rel_err_vs_oracle_per_lattice": gerr,
             "all_converged": all(r.converged for r in res),
-            "tile": solver.tile}
+            "tile": solver.tile, "kernels": bkern}
 
 
 def main():
@@ -503,6 +555,11 @@ def main():
     log(f"dominant kernel {KERNEL_NAMES[dom]} ({dom}): {achieved:.0f} GB/s algorithmic, "
         f"{kern[dom]['avg_us']:.1f} us per launch, {kern[dom]['ms']:.2f} ms per solve")
 
+    # what a kernel moving the complex-float stencil's bytes costs at least
+    floors = launch_floor(kern_c64["stencil"]["bytes_per_launch"]) if "stencil" in kern_c64 else {}
+    log(f"launch floor {floors.get('launch_floor_us', 0):.2f} us, copy of the stencil's bytes "
+        f"{floors.get('copy_same_bytes_us', 0):.2f} us")
+
     # ---- parity against the oracle's stored sample, when one exists for this setup
     err = err_full = None
     gpath = os.path.join(ROOT, "tests", "golden", f"{cfg.name}_mu{mu:g}.json")
@@ -563,11 +620,14 @@ def main():
                    "cycles_complex_float": res.cycles_c64,
                    "matvecs_per_solve": res.matvecs, "sampled_rel_err_vs_oracle": err,
                    "rel_err_vs_oracle": err_full,
-                   "fp64_true_residual_check": {"ok": res.resid_ok, "seconds_per_solve": res.seconds},
+                   "fp64_true_residual_check": {"ok": res.resid_ok},
                    "eigensolve_setup": eig},
         "stencil": {"GBs": kern.get("stencil", {}).get("GBs"),
                     "avg_us": kern.get("stencil", {}).get("avg_us"),
-                    "note": "algorithmic bytes (12 in + 36 link + 12 out complex per site) / time"},
+                    "note": "algorithmic bytes (12 in + 36 link + 12 out complex per site) / time",
+                    "complex_float": {"GBs": kern_c64.get("stencil", {}).get("GBs"),
+                                      "avg_us": kern_c64.get("stencil", {}).get("avg_us"),
+                                      **floors}},
         "roofline": {"bound": "hbm",
                      "kernel": f"{KERNEL_NAMES[dom]} ({dom}: largest summed time in a solve of this "
                                f"configuration; complex-double and complex-float launches)",

@@ -412,7 +412,10 @@ class BatchedSignSolver:
                       for _ in range(self.nsys)]
         self.tile = None
 
-    def __call__(self, bs, xs=None, raise_on_error=True):
+    def __call__(self, bs, xs=None, raise_on_error=True, kernel_times=False):
+        """kernel_times: plain launches with HIP events per launch class
+        (slower); the per-class times and algorithmic bytes of the live
+        systems go to self.kernel_times."""
         if len(bs) != self.nsys:
             raise ValueError(f"expected {self.nsys} sources, got {len(bs)}")
         for z, b in enumerate(bs):
@@ -430,8 +433,19 @@ class BatchedSignSolver:
             st[z].hist_beta = C.cast(hb, C.POINTER(C.c_double))
             st[z].hist_leak = C.cast(hl, C.POINTER(C.c_double))
             st[z].hist_cap = self.hist_cap
+        times = None
+        if kernel_times:
+            times = L.SkKernelTimes()
+            st[0].times = C.pointer(times)
         status = self.lib.sign_apply_batched(self.nsys, self._desc, C.byref(self.params), st,
                                              _ptr(self.ws), self.ws.numel(), _stream())
+        if times is not None:
+            self.kernel_times = {
+                name: {"ms": times.ms[i], "launches": int(times.launches[i]),
+                       "avg_us": 1e3 * times.ms[i] / times.launches[i],
+                       "bytes_per_launch": times.bytes[i] / times.launches[i],
+                       "GBs": times.bytes[i] / (times.ms[i] * 1e-3) / 1e9 if times.ms[i] > 0 else None}
+                for i, name in enumerate(L.SK_KERNEL_CLASSES) if times.launches[i]}
         if raise_on_error and status != L.SK_OK:
             L.check(status)
         a, b_, c_ = C.c_int(), C.c_int(), C.c_int()

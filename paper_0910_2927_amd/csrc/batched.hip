@@ -12,6 +12,8 @@
 #include "dcgs2_dev.h"
 #include "small_dev.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <atomic>
 #include <map>
@@ -572,39 +574,95 @@ hipStream_t batch_capture_stream() {
   return cs;
 }
 
+// Per-kernel timing of a batched cycle (plain launches, no graph): the
+// host copies of the descriptors and of the activity mask give each launch
+// class its algorithmic bytes, summed over the systems live in the cycle.
+// A null pointer means no timing.
+struct BTiming {
+  KTimer* tm;
+  const std::vector<BSys>* hs;
+  const std::vector<BGroup>* hg;
+  const std::vector<int>* act;
+  bool on() const { return tm && tm->on(); }
+  // sum over live systems of f(system); 0 when timing is off
+  template <typename F> double sum(F f) const {
+    double t = 0.0;
+    if (!on()) return t;
+    for (size_t z = 0; z < hs->size(); ++z)
+      if ((*act)[z]) t += f((*hs)[z]);
+    return t;
+  }
+  KTimer::Ext ext(int cls, double bytes) const { return on() ? tm->begin_ext(cls, bytes) : KTimer::Ext{}; }
+};
+
+// A launch that stamps the timing events when they are set.
+template <typename F, typename... Args>
+hipError_t blaunch(F kern, dim3 grid, dim3 block, hipStream_t s, hipEvent_t t0, hipEvent_t t1, Args... args) {
+  if (t0 || t1) hipExtLaunchKernelGGL(kern, grid, block, 0, s, t0, t1, 0, args...);
+  else hipLaunchKernelGGL(kern, grid, block, 0, s, args...);
+  return hipGetLastError();
+}
+
 // Gram-Schmidt launches of step j: dots, the update of systems still
 // stepping, and the final pass of systems whose restart length is j.
 template <typename T>
-int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
+int enqueue_bgs(const BatchPlan& P, const BTile& tile, int j, hipStream_t s, const BTiming& bt = {}) {
   const int maxrb = brow_blocks(P.nmax, tile.rpt, Pk<T>::P);
   const unsigned maxub = (unsigned)brow_blocks(P.nmax, tile.urt, Pk<T>::P);
-  hipLaunchKernelGGL((k_bdot<T>), dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), 0, s,
-                     P.dsys, P.act, j, tile);
-  SK_LAUNCH(hipGetLastError());
+  const double c = (double)sizeof(T);
+  // V_j^H [u z] (j + 2 vectors; the final pass j = k reads k + 1)
+  const auto ed = bt.ext(SK_K_GS_DOT, bt.sum([&](const BSys& S) {
+    return j <= S.k ? (double)(j < S.k ? j + 2 : j + 1) * S.n * c : 0.0;
+  }));
+  SK_LAUNCH((blaunch(k_bdot<T>, dim3(maxrb, j > 0 ? (j + 7) / 8 : 1, P.nsys), dim3(kBNT), s, ed.t0, ed.t1,
+                     (const BSys*)P.dsys, (const int*)P.act, j, tile)));
   if (gs_reduced(maxrb)) {
-    hipLaunchKernelGGL((k_breduce<T>), dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), 0, s,
-                       P.dsys, P.act, j, tile);
-    SK_LAUNCH(hipGetLastError());
+    const auto er = bt.ext(SK_K_GS_REDUCE, bt.sum([&](const BSys& S) {
+      return j <= S.k ? (double)(brow_blocks(S.n, tile.rpt, Pk<T>::P) + kGsGroups) * (2.0 * j + 2) * 16.0 : 0.0;
+    }));
+    SK_LAUNCH((blaunch(k_breduce<T>, dim3((2 * j + 2 + 63) / 64, kGsGroups, P.nsys), dim3(kBNT), s, er.t0,
+                       er.t1, (const BSys*)P.dsys, (const int*)P.act, j, tile)));
   }
   if (j < P.kmax) {
-    hipLaunchKernelGGL((k_bupdate<T, false>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act,
-                       j, tile);
-    SK_LAUNCH(hipGetLastError());
+    // v_j and u_{j+1}: j + 2 reads, 2 writes
+    const auto eu = bt.ext(SK_K_GS_UPD_DOT, bt.sum([&](const BSys& S) {
+      return j < S.k ? (double)(j + 4) * S.n * c : 0.0;
+    }));
+    SK_LAUNCH((blaunch(k_bupdate<T, false>, dim3(maxub, 1, P.nsys), dim3(kBNT), s, eu.t0, eu.t1,
+                       (const BSys*)P.dsys, (const int*)P.act, j, tile)));
   }
   if (std::find(P.kfinal.begin(), P.kfinal.end(), j) != P.kfinal.end()) {
-    hipLaunchKernelGGL((k_bupdate<T, true>), dim3(maxub, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act,
-                       j, tile);
-    SK_LAUNCH(hipGetLastError());
+    // final second pass of v_k: k + 1 reads, 1 write
+    const auto ef = bt.ext(SK_K_GS_UPD_NORM, bt.sum([&](const BSys& S) {
+      return S.k == j ? (double)(j + 2) * S.n * c : 0.0;
+    }));
+    SK_LAUNCH((blaunch(k_bupdate<T, true>, dim3(maxub, 1, P.nsys), dim3(kBNT), s, ef.t0, ef.t1,
+                       (const BSys*)P.dsys, (const int*)P.act, j, tile)));
   }
   return SK_OK;
 }
 
 template <typename T>
-int enqueue_bstencil(const BatchPlan& P, const BTile& tile, int j, hipStream_t s) {
+int enqueue_bstencil(const BatchPlan& P, const BTile& tile, int j, hipStream_t s, const BTiming& bt = {}) {
   const int maxtiles = (int)((P.nmax / 12 + kSites - 1) / kSites);
-  hipLaunchKernelGGL((k_bstencil<T>), dim3(maxtiles, (P.maxrhs + tile.rhs - 1) / tile.rhs, P.ngroups),
-                     dim3(kBStencilThreads), 0, s, P.dgroups, P.dsys, P.act, j, tile.rhs);
-  SK_LAUNCH(hipGetLastError());
+  // in + out spinors per stepping system, the links once per group with one
+  double bytes = 0.0;
+  if (bt.on()) {
+    const double c = (double)sizeof(T);
+    bytes = bt.sum([&](const BSys& S) { return j < S.k ? 2.0 * S.n * c : 0.0; });
+    for (const BGroup& G : *bt.hg) {
+      bool stepping = false;
+      for (int q = 0; q < G.nsys; ++q) {
+        const int z = G.sys[q];
+        if ((*bt.act)[z] && j < (*bt.hs)[z].k) stepping = true;
+      }
+      if (stepping) bytes += 3.0 * (*bt.hs)[G.sys[0]].n * c;   // 36 complex per site = 3 n
+    }
+  }
+  const auto es = bt.ext(SK_K_STENCIL, bytes);
+  SK_LAUNCH((blaunch(k_bstencil<T>, dim3(maxtiles, (P.maxrhs + tile.rhs - 1) / tile.rhs, P.ngroups),
+                     dim3(kBStencilThreads), s, es.t0, es.t1, (const BGroup*)P.dgroups, (const BSys*)P.dsys,
+                     (const int*)P.act, j, tile.rhs)));
   return SK_OK;
 }
 
@@ -628,37 +686,44 @@ int enqueue_bgs_step(const BatchPlan& P, const BTile& tile, int j, hipStream_t s
 }
 
 template <typename T, typename TN>
-int enqueue_bcycle(const BatchPlan& P, const BTile& tile, hipStream_t s) {
-  const int maxtiles = (int)((P.nmax / 12 + kSites - 1) / kSites);
+int enqueue_bcycle(const BatchPlan& P, const BTile& tile, hipStream_t s, const BTiming& bt = {}) {
   const int maxrb = P.maxrb_defl;
   const unsigned maxrows = (unsigned)((P.nmax + kBNT - 1) / kBNT);
+  const double c = (double)sizeof(T), cn = (double)sizeof(TN);
   for (int j = 0; j <= P.kmax; ++j) {
     if (j < P.kmax) {
-      SK_TRY(enqueue_bstencil<T>(P, tile, j, s));
+      SK_TRY(enqueue_bstencil<T>(P, tile, j, s, bt));
     }
-    SK_TRY(enqueue_bgs<T>(P, tile, j, s));
+    SK_TRY(enqueue_bgs<T>(P, tile, j, s, bt));
   }
-  hipLaunchKernelGGL(k_bsmall, dim3(P.nsys), dim3(kWaves * 64), 0, s, P.dsys, P.act, P.N);
-  SK_LAUNCH(hipGetLastError());
-  hipLaunchKernelGGL((k_bxupdate<T>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys, P.act);
-  SK_LAUNCH(hipGetLastError());
-  hipLaunchKernelGGL(k_bxnorm, dim3(P.nsys), dim3(kBNT), 0, s, P.dsys, P.act);
-  SK_LAUNCH(hipGetLastError());
-  if (P.mmax > 0) {
-    hipLaunchKernelGGL((k_bpdot<T>), dim3(maxrb, (P.mmax + 7) / 8, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                       P.act, 0);
-    SK_LAUNCH(hipGetLastError());
-  }
-  hipLaunchKernelGGL((k_bproject<T, TN, false>), dim3(maxrows, 1, P.nsys), dim3(kBNT), 0, s, P.dsys,
-                     P.act);
-  SK_LAUNCH(hipGetLastError());
+  const auto em = bt.ext(SK_K_SMALL, 0.0);
+  SK_LAUNCH((blaunch(k_bsmall, dim3(P.nsys), dim3(kWaves * 64), s, em.t0, em.t1, (const BSys*)P.dsys,
+                     (const int*)P.act, P.N)));
+  // x += V_k u: k basis vectors, x read and written in FP64
+  const auto ex = bt.ext(SK_K_SOL_UPDATE, bt.sum([&](const BSys& S) {
+    return (double)S.k * S.n * c + 2.0 * S.n * 16.0;
+  }));
+  SK_LAUNCH((blaunch(k_bxupdate<T>, dim3(maxrows, 1, P.nsys), dim3(kBNT), s, ex.t0, nullptr,
+                     (const BSys*)P.dsys, (const int*)P.act)));
+  SK_LAUNCH((blaunch(k_bxnorm, dim3(P.nsys), dim3(kBNT), s, nullptr, ex.t1, (const BSys*)P.dsys,
+                     (const int*)P.act)));
+  // L^H v and v - R (L^H v): L and R once each (m > 0), v read twice, the
+  // restart vector written in the next cycle's precision
+  const auto ep = bt.ext(SK_K_PROJECT, bt.sum([&](const BSys& S) {
+    return (S.m > 0 ? 2.0 * S.m * S.n * 16.0 + S.n * c : 0.0) + S.n * c + S.n * cn;
+  }));
+  if (P.mmax > 0)
+    SK_LAUNCH((blaunch(k_bpdot<T>, dim3(maxrb, (P.mmax + 7) / 8, P.nsys), dim3(kBNT), s, ep.t0, nullptr,
+                       (const BSys*)P.dsys, (const int*)P.act, 0)));
+  SK_LAUNCH((blaunch(k_bproject<T, TN, false>, dim3(maxrows, 1, P.nsys), dim3(kBNT), s,
+                     P.mmax > 0 ? nullptr : ep.t0, ep.t1, (const BSys*)P.dsys, (const int*)P.act)));
   return SK_OK;
 }
 
-int enqueue_bcycle_kind(int kind, const BatchPlan& P, const BTile& tile, hipStream_t s) {
-  if (kind == 0) return enqueue_bcycle<double2, double2>(P, tile, s);
-  if (kind == 1) return enqueue_bcycle<double2, float2>(P, tile, s);
-  return enqueue_bcycle<float2, float2>(P, tile, s);
+int enqueue_bcycle_kind(int kind, const BatchPlan& P, const BTile& tile, hipStream_t s, const BTiming& bt = {}) {
+  if (kind == 0) return enqueue_bcycle<double2, double2>(P, tile, s, bt);
+  if (kind == 1) return enqueue_bcycle<double2, float2>(P, tile, s, bt);
+  return enqueue_bcycle<float2, float2>(P, tile, s, bt);
 }
 
 // The tuner: times the Gram-Schmidt step (dots + update, the bulk of a
@@ -925,6 +990,13 @@ int sign_apply_batched(int nsys, const sk_batch_system* d, const sk_sign_params*
     }
   } guard{exec};
   int nact = nsys;
+  // per-kernel timing (stats[0].times): plain launches instead of graphs
+  KTimer tm;
+  if (stats && stats[0].times) {
+    tm.out = stats[0].times;
+    tm.s = s;
+  }
+  const BTiming bt = tm.on() ? BTiming{&tm, &hs, &hg, &act} : BTiming{};
   for (int cyc = 0; cyc < p->max_cycles && nact > 0; ++cyc) {
     // the whole batch switches to complex float once every active system
     // meets the switch rule (the next cycle's precision is fixed before this
@@ -934,7 +1006,9 @@ int sign_apply_batched(int nsys, const sk_batch_system* d, const sk_sign_params*
       if (act[z] && !(cyc > 0 && st[z].upd_norm <= theta * std::sqrt(st[z].xnorm2))) all_small = false;
     const bool low_next = low || (mixed && cyc > 0 && all_small);
     const int kind = !low ? (low_next ? 1 : 0) : 2;
-    if (!exec[kind]) {
+    if (bt.on()) {
+      SK_TRY(enqueue_bcycle_kind(kind, P, tile, s, bt));
+    } else if (!exec[kind]) {
       hipStream_t cs = batch_capture_stream();
       SK_CHECK(cs != nullptr, "could not create the capture stream");
       SK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -957,9 +1031,10 @@ int sign_apply_batched(int nsys, const sk_batch_system* d, const sk_sign_params*
         return SK_ERR_HIP;
       }
     }
-    SK_HIP(hipGraphLaunch(exec[kind], s));
+    if (!bt.on()) SK_HIP(hipGraphLaunch(exec[kind], s));
     SK_HIP(hipMemcpyAsync(st.data(), P.st, nsys * sizeof(CycleState), hipMemcpyDeviceToHost, s));
     SK_HIP(hipStreamSynchronize(s));
+    tm.flush();
     const bool cur_low = low;
     low = low_next;
     bool changed = false;

@@ -11,8 +11,8 @@ instance:
     python -m paper_0910_2927_amd.profsummary counters DIR [--after NAME]
         | kernel grid=G | counter | dispatches | average value per dispatch |
     python -m paper_0910_2927_amd.profsummary batched DIR
-        | kernel | dispatches | total ms | average us |   (the 84-system batch:
-                                                      grid.z = 84, or 3 for the stencil)
+        | kernel | dispatches | total ms | average us |   (the batched solver's
+                                                      kernels, k_b*, only)
 
 --after NAME keeps the dispatches from the first one whose kernel name
 contains NAME on (e.g. k_fom_poles: a solve's first restart cycle ends with
@@ -55,14 +55,12 @@ def _after(rows, name_idx, after):
     return []
 
 
-def trace(db: str, after: str | None = None, z: tuple | None = None):
+def trace(db: str, after: str | None = None):
     cur = sqlite3.connect(db).cursor()
-    rows = cur.execute("select name, grid_z, duration from kernels order by start").fetchall()
+    rows = cur.execute("select name, duration from kernels order by start").fetchall()
     rows = _after(rows, 0, after)
     agg = OrderedDict()
-    for name, gz, dur in rows:
-        if z is not None and gz not in z:
-            continue
+    for name, dur in rows:
         a = agg.setdefault(short(name), [0, 0.0])
         a[0] += 1
         a[1] += dur
@@ -90,9 +88,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     db = find_db(a.path)
     if a.mode in ("trace", "batched"):
-        # the 84-system batch: per-system kernels have grid.z = 84, the
-        # stencil one z-block per gauge field (3)
-        agg = trace(db, a.after, (84, 3) if a.mode == "batched" else None)
+        agg = trace(db, a.after)
         tot = sum(v[1] for v in agg.values()) or 1.0
         for k, (c, d) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
             if a.mode == "batched" and not k.startswith("k_b"):

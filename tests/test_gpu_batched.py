@@ -120,6 +120,51 @@ def test_batch_is_deterministic_and_drops_finished_systems():
     assert max(r.cycles for r in r1) > r1[1].cycles
 
 
+def test_per_kernel_timing_gives_the_same_iterates():
+    """With per-kernel timing the cycles run as plain launches stamped by
+    HIP events instead of graph replays: bit-identical results in mixed
+    precision (all three cycle kinds), and every launch class reports its
+    launches with the algorithmic bytes of the systems live in each cycle."""
+    import torch
+    from paper_0910_2927_amd import api
+    batch, sig, om, cfg = _mixed_batch(with_c64=True)
+    systems = [(s["op"], s.get("defl_dev")) for s in batch]
+    solver = api.BatchedSignSolver(systems, np.stack([s["sig"] for s in batch]),
+                                   np.stack([s["om"] for s in batch]), 16, tol=1e-10, max_cycles=400,
+                                   precision="mixed")
+    bs = [to_dev(s["b"], s["V"]) for s in batch]
+    announce("sign_apply_batched graph replay vs timed plain launches (mixed)")
+    r1 = solver(bs)
+    r2 = solver(bs, kernel_times=True)
+    for a, b in zip(r1, r2):
+        assert a.converged and b.converged and a.cycles == b.cycles and a.cycles_c64 == b.cycles_c64
+        assert torch.equal(a.x, b.x)
+    assert 0 < r1[0].cycles_c64 < r1[0].cycles
+    kt = solver.kernel_times
+    for cls in ("stencil", "gs_dot", "gs_upd_dot", "gs_upd_norm", "small", "sol_update", "project"):
+        assert kt[cls]["launches"] > 0 and kt[cls]["ms"] > 0
+    cycles = max(r.cycles for r in r1)
+    assert kt["small"]["launches"] == cycles
+    assert kt["stencil"]["launches"] == 16 * cycles
+    # the stencil's bytes: every system steps at every j < 16 while it is
+    # live; links once per gauge field (the first two systems share one)
+    c64 = r1[0].cycles_c64
+    nb = 0.0
+    for j, sys_ in enumerate(batch):
+        n = 12 * sys_["V"]
+        for cyc in range(r1[j].cycles):
+            c = 8 if cyc >= r1[0].cycles - c64 else 16
+            nb += 16 * 2.0 * n * c
+    fields = [batch[0], batch[2], batch[3]]
+    for f, owner in zip(fields, (0, 2, 3)):
+        n = 12 * f["V"]
+        live = max(r1[owner].cycles, r1[1].cycles) if owner == 0 else r1[owner].cycles
+        for cyc in range(live):
+            c = 8 if cyc >= r1[0].cycles - c64 else 16
+            nb += 16 * 3.0 * n * c
+    assert abs(kt["stencil"]["bytes_per_launch"] * kt["stencil"]["launches"] - nb) <= 1e-9 * nb
+
+
 def test_point_and_z2_sources_on_one_field_share_links():
     """The multi-source workload at 6^4: 12 point + 16 Z2 sources on one gauge
     field in one batch; each against the single-system solver, and one
