@@ -549,9 +549,10 @@ def main():
     dom = max(kern, key=lambda c_: kern[c_]["ms"])
     achieved = kern[dom]["GBs"]
     counters = load_counters(os.path.join(ROOT, "profiles", f"{KERNEL_NAMES[dom]}_c3_10x4_counters.txt"))
-    traffic = None
+    traffic = traffic_bytes = None
     if counters and counters.get("source_sha256") == kernel_source_hash(KERNEL_NAMES[dom]):
-        traffic = counters["traffic_bytes_per_launch"] / (kern[dom]["avg_us"] * 1e-6) / 1e9
+        traffic_bytes = counters["traffic_bytes_per_launch"]
+        traffic = traffic_bytes / (kern[dom]["avg_us"] * 1e-6) / 1e9
     log(f"dominant kernel {KERNEL_NAMES[dom]} ({dom}): {achieved:.0f} GB/s algorithmic, "
         f"{kern[dom]['avg_us']:.1f} us per launch, {kern[dom]['ms']:.2f} ms per solve")
 
@@ -633,6 +634,7 @@ def main():
                                f"configuration; complex-double and complex-float launches)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "bytes_per_launch": kern[dom]["bytes_per_launch"],
                      "avg_us": kern[dom]["avg_us"], "launches": kern[dom]["launches"],
                      "ms_per_solve": kern[dom]["ms"]},
