@@ -388,6 +388,8 @@ typedef struct {
   int32_t key;           /* 0: smallest |lambda|, 1: smallest |Re lambda| */
   double tol;            /* relative residual of the converged A^2 Schur vectors */
   int32_t max_restarts;
+  int32_t keep;          /* Schur vectors kept at a thick restart, m + nev_extra ..
+                            ncv - 8 (0: automatic, halfway between the two) */
 } sk_eig_params;
 
 typedef struct {

@@ -88,7 +88,7 @@ class SkOverlapStats(C.Structure):
 
 class SkEigParams(C.Structure):
     _fields_ = [("m", C.c_int32), ("nev_extra", C.c_int32), ("ncv", C.c_int32), ("key", C.c_int32),
-                ("tol", C.c_double), ("max_restarts", C.c_int32)]
+                ("tol", C.c_double), ("max_restarts", C.c_int32), ("keep", C.c_int32)]
 
 
 class SkEigStats(C.Structure):

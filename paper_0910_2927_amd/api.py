@@ -164,14 +164,14 @@ def deflate_project(R, Lv, v, F=None):
 
 
 def deflation_eigensolve(op: WilsonOperator, m, nev_extra=16, ncv=0, key="abs", tol=1e-11,
-                         max_restarts=2000):
+                         max_restarts=2000, keep=0):
     """The m eigenpairs of H_W nearest zero as an oblique projector:
     returns (R (m, n), L (m, n), F (m, m) = sign(T_m), lambda (numpy), stats)."""
     lib = L.load()
     p = L.SkEigParams()
     p.m, p.nev_extra, p.ncv = int(m), int(nev_extra), int(ncv)
     p.key = 0 if key == "abs" else 1
-    p.tol, p.max_restarts = float(tol), int(max_restarts)
+    p.tol, p.max_restarts, p.keep = float(tol), int(max_restarts), int(keep)
     s = op.struct()
     nb = lib.deflation_eigensolve_workspace_bytes(C.byref(s), C.byref(p))
     if nb == 0:

@@ -93,8 +93,8 @@ int rayleigh(EigCtx& e, const double2* X, int p, int adjoint, std::vector<cd>& M
 // Krylov-Schur on op(A)^2 for the nev eigenvalues of smallest real part.
 // On success the first nev basis vectors of e.w.W are orthonormal and span
 // the invariant subspace; T (nev x nev) is the Schur form of op(A)^2 there.
-int krylov_schur(EigCtx& e, int adjoint, int nev, double tol, int max_restarts, uint64_t seed,
-                 std::vector<cd>& Tout, int& restarts, double& resid_out) {
+int krylov_schur(EigCtx& e, int adjoint, int nev, int keep_req, double tol, int max_restarts,
+                 uint64_t seed, std::vector<cd>& Tout, int& restarts, double& resid_out) {
   const int ncv = e.ncv;
   const int64_t n = e.n;
   KrylovWs<double2>& w = e.w;
@@ -156,7 +156,7 @@ int krylov_schur(EigCtx& e, int adjoint, int nev, double tol, int max_restarts, 
     }
     resid_out = resid;
     const bool done = nconv >= nev;
-    const int keep = done ? nev : std::min(ncv - 8, nev + (ncv - nev) / 2);
+    const int keep = done ? nev : (keep_req > 0 ? keep_req : std::min(ncv - 8, nev + (ncv - nev) / 2));
     // thick restart: W[0..keep) = W Q(:, :keep), W[keep] = W[ncv]
     SK_TRY(combine(e, w.W, ncv, Q, ncv, keep, e.Vnew));
     SK_HIP(hipMemcpyAsync(w.W, e.Vnew, (size_t)keep * n * sizeof(double2), hipMemcpyDeviceToDevice, s));
@@ -228,6 +228,8 @@ int deflation_eigensolve(const sk_operator* op, const sk_eig_params* p, double* 
   SK_CHECK(R && L && F && lambda && ws, "NULL argument");
   const int m = p->m, nev = p->m + p->nev_extra, ncv = auto_ncv(p);
   SK_CHECK(ncv >= nev + 8 && ncv <= kMaxK, "ncv = %d must be in [m + nev_extra + 8, %d]", ncv, kMaxK);
+  SK_CHECK(p->keep == 0 || (p->keep >= nev && p->keep <= ncv - 8),
+           "keep = %d must be 0 or in [m + nev_extra, ncv - 8] = [%d, %d]", p->keep, nev, ncv - 8);
   const int64_t n = 12 * volume_of(op);
   SK_CHECK((int64_t)ncv + 1 <= n, "lattice too small for ncv = %d", ncv);
   const size_t need = deflation_eigensolve_workspace_bytes(op, p);
@@ -250,7 +252,7 @@ int deflation_eigensolve(const sk_operator* op, const sk_eig_params* p, double* 
   std::vector<cd> TB, M, Z;
   int rr = 0;
   double resr = 0.0;
-  SK_TRY(krylov_schur(e, 0, nev, p->tol, p->max_restarts, 0x5eed0001ull, TB, rr, resr));
+  SK_TRY(krylov_schur(e, 0, nev, p->keep, p->tol, p->max_restarts, 0x5eed0001ull, TB, rr, resr));
   double window = -1e300;
   for (int i = 0; i < nev; ++i) window = std::max(window, TB[i + (size_t)i * nev].real());
   SK_TRY(rayleigh(e, e.w.W, nev, 0, M));
@@ -290,7 +292,7 @@ int deflation_eigensolve(const sk_operator* op, const sk_eig_params* p, double* 
   std::vector<cd> TBl, Ml, Zl;
   int rl = 0;
   double resl = 0.0;
-  SK_TRY(krylov_schur(e, 1, nev, p->tol, p->max_restarts, 0x5eed0002ull, TBl, rl, resl));
+  SK_TRY(krylov_schur(e, 1, nev, p->keep, p->tol, p->max_restarts, 0x5eed0002ull, TBl, rl, resl));
   SK_TRY(rayleigh(e, e.w.W, nev, 1, Ml));
   if (!dense::schur(nev, Ml, Zl)) {
     set_error("Schur form of the left Rayleigh quotient did not converge");

@@ -21,15 +21,16 @@ def _dev_vecs_to_host(T, V):
     return np.stack([from_dev(T[i], V) for i in range(T.shape[0])], axis=1)
 
 
-@pytest.mark.parametrize("dims,m", [((4, 4, 4, 4), 12), ((3, 4, 5, 6), 20)])
-def test_eigensolver_matches_dense_oracle(dims, m):
+@pytest.mark.parametrize("dims,m,keep", [((4, 4, 4, 4), 12, 0), ((3, 4, 5, 6), 20, 0), ((4, 4, 4, 4), 12, 30)])
+def test_eigensolver_matches_dense_oracle(dims, m, keep):
+    """keep: Schur vectors kept at a thick restart (0: automatic)."""
     from paper_0910_2927_amd import api
     V = si.lattice_volume(dims)
     U = si.gauge_links(dims, 0.5, 300 + V)
     A = dirac.hw_dense(U, dims, 0.25, 0.3)
-    announce(f"eigensolve dims={dims} m={m}")
+    announce(f"eigensolve dims={dims} m={m} keep={keep}")
     op = make_op(U, dims, 0.25, 0.3)
-    R, L, F, lam, st = api.deflation_eigensolve(op, m, nev_extra=16, tol=1e-12)
+    R, L, F, lam, st = api.deflation_eigensolve(op, m, nev_extra=16, tol=1e-12, keep=keep)
     Ro, Lo, lamo, Fo = deflation.lr_dense(A, m)
     # same eigenvalues (the set of the m nearest zero)
     assert np.allclose(np.sort_complex(lam), np.sort_complex(lamo), rtol=0, atol=1e-10)
