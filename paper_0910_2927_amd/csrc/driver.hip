@@ -189,8 +189,7 @@ size_t multishift_fom_restart_workspace_bytes(int k, int npoles) {
 }  // extern "C"
 
 namespace sk {
-__global__ void k_prep_small(double* scale, int k, CycleState* st, const double* beta,
-                             const double2* H, int ld) {
+__global__ void k_prep_small(double* scale, int k, CycleState* st, const double* beta) {
   int t = threadIdx.x;
   for (int i = t; i < k + 2; i += blockDim.x) scale[i] = 1.0;
   if (t == 0) {
@@ -224,7 +223,7 @@ static int msfom_impl(int k, int64_t n, const double2* H, const PoleSet& ps, con
   a.ldh = k + 1;
   a.partial = partial;
   a.counter = counter;
-  hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(256), 0, s, scale, k, st, beta, H, k + 1);
+  hipLaunchKernelGGL(k_prep_small, dim3(1), dim3(256), 0, s, scale, k, st, beta);
   SK_LAUNCH(hipGetLastError());
   SK_LAUNCH(launch_fom_small(a, k, ps, rho, Y, U, ucoef, X ? ycoef : nullptr, s));
   TsEpiArgs e = epi_of(EPI_NONE, a);

@@ -37,10 +37,6 @@ __global__ void k_start_vector(double2* v, int64_t n, uint64_t seed) {
   const uint64_t a = splitmix64(seed ^ (2 * (uint64_t)i)), b = splitmix64(seed ^ (2 * (uint64_t)i + 1));
   v[i] = make_double2((double)(a >> 11) * 0x1.0p-52 - 1.0, (double)(b >> 11) * 0x1.0p-52 - 1.0);
 }
-__global__ void k_fill(double* p, int64_t cnt, double val) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < cnt) p[i] = val;
-}
 
 struct EigCtx {
   const sk_operator* op;
