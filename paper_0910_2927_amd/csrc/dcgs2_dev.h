@@ -52,15 +52,16 @@ __device__ inline void reduce_cols(const double2* __restrict__ src, int nrows, i
     const int i = i0 + lane;
     double2 acc = z2();
     if (i < pr) {
-      int b = wid;
-      for (; b + 7 * NW < nrows; b += 8 * NW) {
+      // batches of 8 rows per wave, all loads issued before the sums (a
+      // partial last batch reads zeros past nrows): the same order of
+      // additions as one row at a time, without a chain of dependent loads
+      for (int b = wid; b < nrows; b += 8 * NW) {
         double2 v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = src[(size_t)(b + u * NW) * pr + i];
+        for (int u = 0; u < 8; ++u) v[u] = b + u * NW < nrows ? src[(size_t)(b + u * NW) * pr + i] : z2();
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
       }
-      for (; b < nrows; b += NW) acc = cadd(acc, src[(size_t)b * pr + i]);
     }
     scratch[threadIdx.x] = acc;
     __syncthreads();
@@ -299,14 +300,43 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
   __shared__ double sc[4];            // beta, d/beta (re, im), flag
   __shared__ double2 cd;
   const int pr = 2 * j + 2;
-  reduce_cols<BT>(part, nrb, pr, sums, scratch);
   const int tid = threadIdx.x;
+  using K = Pk<T>;
+  using PT = typename K::type;
+  PT* u = reinterpret_cast<PT*>(W + (int64_t)j * ldq);
+  PT* zv = reinterpret_cast<PT*>(W + (int64_t)(j + 1) * ldq);
+  // Operands that do not depend on the partial sums are loaded first, so
+  // that their latency overlaps the reductions: this thread's entry of
+  // s_{j-1}, its first four entries of H_j and its s_{j-1} entry for H_j t,
+  // and (with lanes sharing a row pack) u_j, z of its first row pack.
+  constexpr int G = BW;   // threads per output of H_j t
+  const int lend = (fresh ? j : j - 1);
+  const double2 sp_t = (!fresh && tid < j) ? s_prev[tid] : z2();
+  const int ih = tid / G, gh = tid % G;
+  double2 sp_h = z2();
+  double2 hpre[4];
+  bool hpre_ok = false;
+  if (!FINAL && ih < j) {
+    if (!fresh && j > 0 && gh == 0) sp_h = s_prev[ih];
+    const int l = max(0, ih - 1) + gh;
+    if (l + 3 * G < lend) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) hpre[q] = arn.H[(size_t)(l + q * G) * arn.ldh + ih];
+      hpre_ok = true;
+    }
+  }
+  PT ru0, rz0;   // (with one lane per row pack the registers are needed for the basis loads)
+  if (SPLIT > 1 && r0 * K::P < n) {
+    ru0 = u[r0];
+    if (!FINAL) rz0 = zv[r0];
+  }
+  reduce_cols<BT>(part, nrb, pr, sums, scratch);
   // |t|^2 and |s_{j-1}|^2
   double tt = 0.0, ss = 0.0;
   for (int i = tid; i < j; i += BT) {
     ct[i] = sums[i];
     tt += cabs2(sums[i]);
-    if (!fresh) ss += cabs2(s_prev[i]);
+    if (!fresh) ss += cabs2(i == tid ? sp_t : s_prev[i]);
   }
   tt = wave_sum(tt);
   ss = wave_sum(ss);
@@ -359,13 +389,16 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
     // consecutive threads share an output i (strided partial sums, then a
     // fixed-order combination over the group), so the loads of H are
     // spread over the block instead of serialised in j threads.
-    constexpr int G = BW;
-    const int lend = (fresh ? j : j - 1);
     for (int i0 = 0; i0 < j; i0 += BT / G) {
       const int i = i0 + tid / G, g = tid % G;
       double2 ht = z2();
       if (i < j) {
         int l = max(0, i - 1) + g;
+        if (i0 == 0 && hpre_ok) {   // the first four, loaded at the start
+#pragma unroll
+          for (int q = 0; q < 4; ++q) ht = cadd(ht, cmul(hpre[q], ct[l + q * G]));
+          l += 4 * G;
+        }
         for (; l + 3 * G < lend; l += 4 * G) {
           double2 hv[4];
 #pragma unroll
@@ -381,7 +414,7 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
         ht.y += __shfl_xor(ht.y, off, 64);
       }
       if (g == 0 && i < j) {
-        if (!fresh && j > 0) ht = cadd(ht, cmul(cadd(s_prev[i], ct[i]), ct[j - 1]));
+        if (!fresh && j > 0) ht = cadd(ht, cmul(cadd(i0 == 0 ? sp_h : s_prev[i], ct[i]), ct[j - 1]));
         const double2 si = cscale(csub(sums[j + i], ht), ib);     // (p_i - (H_j t)_i) / beta
         cs[i] = si;
         ce[i] = cadd(cscale(ht, ib), si);                         // c_i = (H_j t)_i / beta + s_i
@@ -415,10 +448,6 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
     __syncthreads();
   }
   static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4, "1, 2 or 4 lanes per row pack");
-  using K = Pk<T>;
-  using PT = typename K::type;
-  PT* u = reinterpret_cast<PT*>(W + (int64_t)j * ldq);
-  PT* zv = reinterpret_cast<PT*>(W + (int64_t)(j + 1) * ldq);
   const int sub = SPLIT > 1 ? (int)(threadIdx.x & (SPLIT - 1)) : 0;
   for (int q = 0; q < urt; ++q) {
     const int64_t rp = r0 + (int64_t)q * (BT / SPLIT);
@@ -427,9 +456,9 @@ __device__ inline void dc_update_body(T* __restrict__ W, int64_t ldq, int j, int
 #pragma unroll
     for (int p = 0; p < K::P; ++p) at[p] = ae[p] = z2();
     constexpr int B = 16 / SPLIT;   // basis loads in flight per thread
-    const PT ru = u[rp];
+    const PT ru = (SPLIT > 1 && q == 0) ? ru0 : u[rp];
     PT rz;
-    if (!FINAL) rz = zv[rp];
+    if (!FINAL) rz = (SPLIT > 1 && q == 0) ? rz0 : zv[rp];
     int i = sub;   // vectors i, i + SPLIT, ...
     for (; i + SPLIT * (B - 1) < j; i += SPLIT * B) {
       PT raw[B];
