@@ -62,7 +62,7 @@ CONFIGS = {
     # x* at 1e-9 (the target is 1e-8), and complex float takes over at a
     # relative update of 1e-2 (the FP64 residual check confirms the result)
     "c3": Config("c3", (10, 10, 10, 10), 0.7, (0.1, 0.3, 0.5), s=8, k=60, m=40, tol=1e-9,
-                 precision="mixed", mixed_switch=1e-2, scales={0.1: 2.435, 0.3: 2.422}),
+                 precision="mixed", mixed_switch=1e-2, scales={0.1: 2.435, 0.3: 2.422, 0.5: 2.514}),
     # c3 with the Kenney-Laub order raised to s = 32 (64 poles): the scalar
     # error bound 2 rho^{2s} of g_s on the scaled segment [a, lambda_max]
     # falls from ~1e-2 (s = 8) to ~4e-9, so the result approximates
