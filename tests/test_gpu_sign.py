@@ -244,6 +244,26 @@ def test_longest_restart_and_most_poles(k, s):
     assert err <= TOL_FP64
 
 
+def test_largest_deflation_space():
+    """m = 128, the library's limit for the deflation space (coefficients of
+    the projection held in LDS, 16 chunks of 8 columns in the dots), with 64
+    poles, against the oracle's x* with the same LR deflation."""
+    import torch
+    from paper_0910_2927_amd import api
+    dims = (4, 4, 4, 4)
+    V, U, b, A = _problem(dims, 0.6, 0.3, 131, 132)
+    R, L, lam, F = deflation.lr_dense(A, 128)
+    sig, om = rational.kl_first_order(32, 1.2)
+    announce("sign_apply 4^4 m=128 poles=64 k=40")
+    op = make_op(U, dims, 0.25, 0.3)
+    res = api.sign_apply(op, to_dev(b, V), sig, om, 40, tol=1e-11, max_cycles=400,
+                         R=vecs_to_dev(R, V), Lv=vecs_to_dev(L, V), F=torch.from_numpy(F).to(torch_dev()))
+    assert res.converged
+    err = rel(from_dev(res.x, V), xstar.xstar_dense(A, b, sig, om, R, L, F))
+    print(f"m=128: cycles={res.cycles} err={err:.2e} leak={res.leaks[-1]:.1e}")
+    assert err <= TOL_FP64
+
+
 def test_shifted_residuals_stay_collinear_across_restarts():
     """Sect. 3: after every restart the residuals of all shifted systems are
     multiples of one vector (the restart vector), which is what lets one
