@@ -339,7 +339,11 @@ typedef struct {
  *   are ignored; X_shift must be NULL.  SK_PREC_MIXED switches the whole
  *   batch to the complex-float basis once every active system meets the
  *   switch rule.
- * stats: host, nullable, nsys entries (times is not filled).
+ * stats: host, nullable, nsys entries.  If stats[0].times is set, the
+ *   cycles run as plain launches stamped by HIP events (slower; the same
+ *   results bit for bit) and stats[0].times receives, per launch class,
+ *   the time and the algorithmic bytes of the systems live in each cycle;
+ *   the times of the other entries are not filled.
  * Returns SK_OK if every system converged, else the status of a failing
  * one (every x still holds its iterate; stats[z].converged says which).
  * Workspace: sign_apply_batched_workspace_bytes (0 = invalid arguments).
