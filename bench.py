@@ -434,9 +434,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the sign(H_W)b solve "
-                                   "shards by source (no communication) -- run one process per "
-                                   "GPU with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU (--gpus 1); the sign(H_W)b "
+                                   "solve shards by source with no communication, so N GPUs run "
+                                   "N independent processes of this benchmark"}))
         sys.exit(2)
 
     import torch
