@@ -20,7 +20,8 @@ FILES = sorted(glob.glob(os.path.join(HERE, "*.json")))
 
 def test_there_are_stored_values_for_every_large_config():
     names = {os.path.basename(f) for f in FILES}
-    for must in ["c6_mu0.3.json", "c2_mu0.3.json", "c3_mu0.3.json", "cg_mu0.3.json", "c2_mu0.1.json"]:
+    for must in ["c6_mu0.3.json", "c2_mu0.3.json", "c3_mu0.3.json", "cg_mu0.3.json", "c2_mu0.1.json",
+                 "c3_mu0.1.json", "c3_mu0.5.json", "c3s_mu0.3.json"]:
         assert must in names
 
 
